@@ -1,0 +1,307 @@
+/*
+ * rbm_oracle.c -- plain, slow FP64 reference of one RBM-1 time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library and its Python binding) never calls it, and the two
+ * share no source, header, table or helper.
+ *
+ * What is computed, and where the paper defines it (Jin, Li & Liu, "Random
+ * Batch Methods (RBM) for interacting particle systems", arXiv:1812.10575):
+ *
+ *   - the binary particle system, eq. (1.2):
+ *       dX^i = -grad V(X^i) dt + 1/(N-1) sum_{j != i} K(X^i - X^j) dt + sigma dB^i
+ *   - RBM-1, Sec. 2.1 / Algorithm 1: at every step divide the particles into
+ *     batches of p at random, then evolve each batch with the interaction
+ *     restricted to the batch and the prefactor 1/(p-1), eq. (2.3)
+ *   - the random division is a uniformly random permutation whose first p
+ *     entries form batch 1, the next p batch 2, and so on (Sec. 2.1, the
+ *     remark on the cost of the division)
+ *   - if p does not divide N the last batch is allowed to differ in size
+ *     (Sec. 2.1, the parenthetical on p dividing N; Sec. 2.3, item on
+ *     unequal batch sizes).  Reading used here: the N mod p leftover
+ *     particles join the last batch, so every batch has at least p >= 2
+ *     members and 1/(s-1) is defined for the batch size s.
+ *   - forward Euler (Euler-Maruyama when sigma > 0) solves the batch SDE over
+ *     one step (Sec. 4.1 uses forward Euler for every step).
+ *
+ * The paper leaves the random-number source open (it names MATLAB's randperm).
+ * This oracle fixes it as follows; the GPU library implements the same
+ * definitions independently.
+ *
+ *   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ *   easy as 1, 2, 3", SC'11): a 4x32-bit counter c, a 2x32-bit key k; each of
+ *   10 rounds multiplies c0 and c2 by two fixed odd constants, recombines the
+ *   high and low halves with c1, c3 and the key by xor, and the key is bumped
+ *   by two Weyl constants between rounds.
+ *
+ *   key = (seed mod 2^32, seed div 2^32)
+ *   PERM word of slot k at step m : Philox(c = (k >> 2, m, 0, sys))[k & 3]
+ *   NOISE of particle id i, step m: Philox(c = (i, m, 1, sys)) -> 4 words
+ *   uniform(w)  = (2 * (w >> 9) + 1) * 2^-24   (24 significant bits: the same
+ *                 number in FP32 and FP64)
+ *   normals     : Box-Muller on (u0,u1) -> (z0,z1), on (u2,u3) -> (z2,z3)
+ *
+ *   The permutation of step m: the particles sit in "slots" 0..N-1 (the
+ *   order left by the previous step; the identity before the first step).
+ *   Slot k draws the PERM word w_k and gets the unique 64-bit key
+ *   (w_k << 32) | id(k).  Sorting the keys ascending gives the permutation;
+ *   it is uniform because the words are i.i.d. and independent of the slot
+ *   order (ties on w, probability 2^-32 per pair, resolve by id).  The sorted
+ *   order becomes the next step's slot order.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11)                                                     */
+/* ------------------------------------------------------------------------ */
+
+static void philox_round(uint32_t c[4], const uint32_t k[2])
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    const uint32_t n1 = lo1;
+    const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    const uint32_t n3 = lo0;
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+}
+
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+static void philox_seeded(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                          uint32_t c3, uint32_t out[4])
+{
+    const uint32_t ctr[4] = {c0, c1, c2, c3};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    ora_philox4x32_10(ctr, key, out);
+}
+
+/* 24-bit uniform in (0,1): exactly representable in FP32 and FP64. */
+double ora_uniform(uint32_t w)
+{
+    return (double)(2u * (w >> 9) + 1u) * (1.0 / 16777216.0);
+}
+
+/* PERM word of slot k at step m. */
+uint32_t ora_perm_word(uint64_t seed, uint32_t sys, uint32_t m, uint32_t slot)
+{
+    uint32_t o[4];
+    philox_seeded(seed, slot >> 2, m, 0u, sys, o);
+    return o[slot & 3u];
+}
+
+/* Four standard normals of particle id at step m (Box-Muller on the NOISE
+ * block).  The Brownian increment of eq. (1.2) over one step is
+ * sqrt(dt) * z. */
+void ora_normals(uint64_t seed, uint32_t sys, uint32_t m, uint32_t id, double z[4])
+{
+    uint32_t o[4];
+    philox_seeded(seed, id, m, 1u, sys, o);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int h = 0; h < 2; ++h) {
+        const double u0 = ora_uniform(o[2 * h]);
+        const double u1 = ora_uniform(o[2 * h + 1]);
+        const double r = sqrt(-2.0 * log(u0));
+        z[2 * h] = r * cos(two_pi * u1);
+        z[2 * h + 1] = r * sin(two_pi * u1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model: the pair kernel K and the external field -grad V of eq. (1.2)     */
+/* ------------------------------------------------------------------------ */
+
+enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2 };
+
+typedef struct {
+    int32_t d;          /* space dimension, 1..3 */
+    int32_t kernel;     /* ORA_K_* */
+    double kparam;      /* softening a of the kernels below */
+    double beta;        /* V(x) = beta |x|^2 / 2, so -grad V = -beta x */
+    double sigma;       /* noise amplitude */
+    double dt;          /* time step tau */
+    uint64_t seed;
+    uint32_t sys;
+} ora_params;
+
+/* The three interaction kernels used by the workloads:
+ *   GAUSS       K(x) = -x exp(-|x|^2)
+ *   SOFTCOULOMB K(x) = x / (|x|^2 + a)         (a = eps^2; a = 1 gives the
+ *                                               Sec. 4.1 kernel x/(1+x^2))
+ *   ATTREP      K(x) = x / (|x|^2 + a) - x
+ * All three are odd: K(-x) = -K(x), K(0) = 0. */
+void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, double *out)
+{
+    double r2 = 0.0;
+    for (int k = 0; k < d; ++k) r2 += x[k] * x[k];
+    double s;
+    switch (kernel) {
+    case ORA_K_GAUSS:       s = -exp(-r2); break;
+    case ORA_K_SOFTCOULOMB: s = 1.0 / (r2 + a); break;
+    case ORA_K_ATTREP:      s = 1.0 / (r2 + a) - 1.0; break;
+    default:                s = 0.0; break;
+    }
+    for (int k = 0; k < d; ++k) out[k] = s * x[k];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random division (Sec. 2.1)                                               */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* slots[k] = id of the particle in slot k (input); perm[r] = id at sorted
+ * rank r (output; may alias slots). */
+void ora_permutation(const ora_params *prm, int64_t n, uint32_t m,
+                     const uint32_t *slots, uint32_t *perm)
+{
+    uint64_t *keys = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    for (int64_t k = 0; k < n; ++k) {
+        const uint64_t w = ora_perm_word(prm->seed, prm->sys, m, (uint32_t)k);
+        keys[k] = (w << 32) | (uint64_t)slots[k];
+    }
+    qsort(keys, (size_t)n, sizeof(uint64_t), cmp_u64);
+    for (int64_t r = 0; r < n; ++r) perm[r] = (uint32_t)(keys[r] & 0xffffffffu);
+    free(keys);
+}
+
+/* Batch of sorted rank r: consecutive groups of p; the last of the
+ * floor(N/p) groups also takes the N mod p leftover ranks. */
+void ora_batch_of(int64_t n, int32_t p, int64_t r, int64_t *start, int64_t *end)
+{
+    const int64_t nb = n / p;
+    int64_t q = r / p;
+    if (q > nb - 1) q = nb - 1;
+    *start = q * p;
+    *end = (q == nb - 1) ? n : (q + 1) * p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forces                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* RBM-1 batch force of every particle for a given division perm (eq. (2.3)):
+ *   F_i = 1/(s-1) sum_{j in C(i), j != i} K(X_i - X_j),  s = |C(i)|.
+ * x and f are N x d, indexed by particle id. */
+void ora_rbm_forces(const ora_params *prm, int64_t n, int32_t p,
+                    const double *x, const uint32_t *perm, double *f)
+{
+    const int d = prm->d;
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t b0, b1;
+        ora_batch_of(n, p, r, &b0, &b1);
+        const uint32_t i = perm[r];
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t t = b0; t < b1; ++t) {
+            const uint32_t j = perm[t];
+            if (j == i) continue;
+            double dx[3], kv[3];
+            for (int k = 0; k < d; ++k) dx[k] = x[(int64_t)i * d + k] - x[(int64_t)j * d + k];
+            ora_pair_kernel(prm->kernel, d, prm->kparam, dx, kv);
+            for (int k = 0; k < d; ++k) acc[k] += kv[k];
+        }
+        const double inv = 1.0 / (double)(b1 - b0 - 1);
+        for (int k = 0; k < d; ++k) f[(int64_t)i * d + k] = acc[k] * inv;
+    }
+}
+
+/* Exact interaction force of eq. (1.2) for the particles listed in ids:
+ *   F_i = 1/(N-1) sum_{j != i} K(X_i - X_j). */
+void ora_direct_forces(const ora_params *prm, int64_t n, const double *x,
+                       const uint32_t *ids, int64_t nids, double *f)
+{
+    const int d = prm->d;
+    for (int64_t t = 0; t < nids; ++t) {
+        const uint32_t i = ids[t];
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == (int64_t)i) continue;
+            double dx[3], kv[3];
+            for (int k = 0; k < d; ++k) dx[k] = x[(int64_t)i * d + k] - x[j * d + k];
+            ora_pair_kernel(prm->kernel, d, prm->kparam, dx, kv);
+            for (int k = 0; k < d; ++k) acc[k] += kv[k];
+        }
+        for (int k = 0; k < d; ++k) f[t * d + k] = acc[k] / (double)(n - 1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time stepping                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* One Euler-Maruyama step of  dX = (-beta X + F) dt + sigma dB  for every
+ * particle, all forces taken at the old positions:
+ *   X_i <- X_i + dt (-beta X_i + F_i) + sigma sqrt(dt) z_i. */
+static void euler_update(const ora_params *prm, int64_t n, uint32_t m,
+                         const double *f, double *x)
+{
+    const int d = prm->d;
+    const double sq = sqrt(prm->dt);
+    for (int64_t i = 0; i < n; ++i) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (prm->sigma != 0.0) ora_normals(prm->seed, prm->sys, m, (uint32_t)i, z);
+        for (int k = 0; k < d; ++k) {
+            const double xi = x[i * d + k];
+            x[i * d + k] = xi + prm->dt * (-prm->beta * xi + f[i * d + k])
+                         + prm->sigma * sq * z[k];
+        }
+    }
+}
+
+/* One RBM-1 step m (Algorithm 1): draw the division from the slot order,
+ * compute batch forces at the old positions, update.  slots is replaced by
+ * the new order (the sorted permutation). */
+void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
+                  double *x, uint32_t *slots)
+{
+    const int d = prm->d;
+    double *f = (double *)malloc((size_t)n * d * sizeof(double));
+    ora_permutation(prm, n, m, slots, slots);
+    ora_rbm_forces(prm, n, p, x, slots, f);
+    euler_update(prm, n, m, f, x);
+    free(f);
+}
+
+/* nsteps consecutive RBM-1 steps m0, m0+1, ... */
+void ora_rbm_run(const ora_params *prm, int64_t n, int32_t p, uint32_t m0,
+                 int64_t nsteps, double *x, uint32_t *slots)
+{
+    for (int64_t s = 0; s < nsteps; ++s)
+        ora_rbm_step(prm, n, p, (uint32_t)(m0 + s), x, slots);
+}
+
+/* One step of the fully coupled system with the same update and the same
+ * noise as the RBM-1 step m. */
+void ora_direct_step(const ora_params *prm, int64_t n, uint32_t m, double *x)
+{
+    const int d = prm->d;
+    double *f = (double *)malloc((size_t)n * d * sizeof(double));
+    uint32_t *ids = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
+    ora_direct_forces(prm, n, x, ids, n, f);
+    euler_update(prm, n, m, f, x);
+    free(ids);
+    free(f);
+}

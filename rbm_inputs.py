@@ -1,0 +1,61 @@
+"""Seeded synthetic inputs for the RBM-1 workloads.
+
+This module holds no arithmetic of the method: it only draws initial
+particle positions and ensemble sizes.  Both the GPU path's tests and the
+oracle receive what it returns, so neither side generates its own inputs.
+The draws use numpy's Philox bit generator (a 4x64 counter-based generator,
+unrelated to the Philox4x32-10 streams the method itself draws from).
+
+Workload shapes (particles are i.i.d., as the paper assumes for the initial
+data of eq. (1.2)):
+  gauss2d     d=2, X0 ~ N(0, I)              (Gaussian-attraction workload)
+  dyson1d     d=1, X0 ~ U[-3, 3]             (1-D softened-Coulomb workload)
+  attrep3d    d=3, X0 ~ N(0, I)              (3-D attraction-repulsion)
+  semicircle  d=1, X0 ~ sqrt(4 - x^2)/(2 pi) (the initial law of Sec. 4.1)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _gen(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(int(seed)))
+
+
+def normal(n: int, d: int, seed: int = 1) -> np.ndarray:
+    """N x d float32 array of i.i.d. standard normals."""
+    return _gen(seed).standard_normal((n, d), dtype=np.float32)
+
+
+def uniform(n: int, d: int, lo: float, hi: float, seed: int = 1) -> np.ndarray:
+    """N x d float32 array of i.i.d. U[lo, hi]."""
+    u = _gen(seed).random((n, d), dtype=np.float64)
+    return (lo + (hi - lo) * u).astype(np.float32)
+
+
+def semicircle(n: int, radius: float = 2.0, seed: int = 1) -> np.ndarray:
+    """N x 1 float32 draws from the semicircle density of the given radius
+    (the x-coordinate of a uniform point in the disc of that radius)."""
+    g = _gen(seed)
+    r = radius * np.sqrt(g.random(n))
+    th = 2.0 * np.pi * g.random(n)
+    return (r * np.cos(th)).astype(np.float32).reshape(n, 1)
+
+
+def ensemble_sizes(s: int, nmin: int = 64, nmax: int = 65536, seed: int = 1) -> np.ndarray:
+    """S system sizes, log-uniform on [nmin, nmax] (int64)."""
+    u = _gen(seed).random(s)
+    n = np.floor(nmin * (nmax / nmin) ** u).astype(np.int64)
+    return np.clip(n, nmin, nmax)
+
+
+def workload(name: str, n: int, seed: int = 1) -> np.ndarray:
+    if name == "gauss2d":
+        return normal(n, 2, seed)
+    if name == "dyson1d":
+        return uniform(n, 1, -3.0, 3.0, seed)
+    if name == "attrep3d":
+        return normal(n, 3, seed)
+    if name == "semicircle":
+        return semicircle(n, 2.0, seed)
+    raise ValueError(f"unknown workload {name!r}")

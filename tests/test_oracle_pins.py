@@ -1,0 +1,369 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed forms, exact combinatorial identities of
+Lemma 3.1 (enumerated over every division), conservation laws of the
+update, and the error rate of Sec. 4.1 / Theorem 3.1.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import rbm_inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# helpers: divisions enumerated independently of the oracle
+# --------------------------------------------------------------------------
+
+def _equal_partitions(items, p):
+    if not items:
+        yield []
+        return
+    first, rest = items[0], items[1:]
+    for others in itertools.combinations(rest, p - 1):
+        block = (first,) + others
+        left = [i for i in rest if i not in others]
+        for tail in _equal_partitions(left, p):
+            yield [block] + tail
+
+
+def divisions(n, p):
+    """Every division of {0..n-1} into floor(n/p) batches; when p does not
+    divide n the last batch has p + n mod p members."""
+    if n % p == 0:
+        yield from _equal_partitions(list(range(n)), p)
+        return
+    big = p + n % p
+    for bigblock in itertools.combinations(range(n), big):
+        rest = [i for i in range(n) if i not in bigblock]
+        for part in _equal_partitions(rest, p):
+            yield part + [bigblock]
+
+
+def canon(perm, p):
+    """Division of a permutation: consecutive groups of p, remainder merged."""
+    n = len(perm)
+    nb = n // p
+    blocks = [tuple(sorted(perm[q * p:(q + 1) * p])) for q in range(nb - 1)]
+    blocks.append(tuple(sorted(perm[(nb - 1) * p:])))
+    return tuple(sorted(blocks))
+
+
+def M(n, p):
+    return math.factorial(n) // (math.factorial(p) ** (n // p) * math.factorial(n // p))
+
+
+# --------------------------------------------------------------------------
+# random streams
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers(ora):
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = ora.philox4x32_10(v[0:4], v[4:6])
+        assert [int(o) for o in out] == v[6:10]
+
+
+def test_uniform_is_24bit_and_exact_in_fp32(ora):
+    assert ora.uniform(0) == 2.0 ** -24
+    assert ora.uniform(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    assert ora.uniform(0x80000000) == 0.5 + 2.0 ** -24
+    rng = np.random.default_rng(5)
+    for w in rng.integers(0, 2 ** 32, 2000, dtype=np.uint64):
+        u = ora.uniform(int(w))
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u
+
+
+def test_stream_counter_layout(ora):
+    seed, sys = 0x1234567890ABCDEF, 7
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for m in (0, 1, 99):
+        for slot in (0, 1, 2, 3, 4, 1023, 12345):
+            blk = ora.philox4x32_10([slot >> 2, m, 0, sys], key)
+            assert ora.perm_word(seed, sys, m, slot) == int(blk[slot & 3])
+
+
+def test_box_muller_inverts_to_the_noise_uniforms(ora):
+    """z0^2 + z1^2 = -2 ln u0 and atan2(z1, z0) = 2 pi u1 (mod 2 pi) for the
+    uniforms of the NOISE block (i, m, 1, sys); same for (z2, z3)."""
+    seed, sys = 99, 3
+    key = [seed, 0]
+    for pid in (0, 5, 77):
+        for m in (0, 3):
+            blk = ora.philox4x32_10([pid, m, 1, sys], key)
+            u = [ora.uniform(int(w)) for w in blk]
+            z = ora.normals(seed, sys, m, pid)
+            for h in range(2):
+                a, b = z[2 * h], z[2 * h + 1]
+                assert a * a + b * b == pytest.approx(-2.0 * math.log(u[2 * h]), rel=1e-13)
+                ang = math.atan2(b, a) % (2.0 * math.pi)
+                assert ang == pytest.approx(2.0 * math.pi * u[2 * h + 1], abs=1e-12)
+
+
+def test_normals_are_standard_normal(ora):
+    z = np.concatenate([ora.normals(1, 0, 0, i) for i in range(16384)])
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.03
+
+
+# --------------------------------------------------------------------------
+# the model: kernels at points where their values are known in closed form
+# --------------------------------------------------------------------------
+
+def test_kernel_closed_forms(ora):
+    # Gaussian attraction: |K| peaks at |x| = 1/sqrt 2 with value e^{-1/2}/sqrt 2,
+    # pointing to the origin.
+    r = 1.0 / math.sqrt(2.0)
+    kv = ora.pair_kernel(ora.K_GAUSS, 2, 0.0, [r, 0.0])
+    assert kv[0] == pytest.approx(-math.exp(-0.5) / math.sqrt(2.0), rel=1e-15)
+    assert kv[1] == 0.0
+    # softened Coulomb in 1-D: K(eps) = 1/(2 eps)
+    eps = 1e-3
+    assert ora.pair_kernel(ora.K_SOFTCOULOMB, 1, eps * eps, [eps])[0] == pytest.approx(1.0 / (2 * eps), rel=1e-14)
+    # a = 1 is the kernel of Sec. 4.1, x/(1+x^2): value 1/2 at x = 1
+    assert ora.pair_kernel(ora.K_SOFTCOULOMB, 1, 1.0, [1.0])[0] == pytest.approx(0.5, rel=1e-15)
+    # attraction-repulsion vanishes on |x|^2 = 1 - a, repels inside, attracts outside
+    a = 0.01
+    s = math.sqrt(1.0 - a) / math.sqrt(3.0)
+    assert np.max(np.abs(ora.pair_kernel(ora.K_ATTREP, 3, a, [s, s, s]))) < 1e-15
+    assert ora.pair_kernel(ora.K_ATTREP, 3, a, [0.5, 0, 0])[0] > 0
+    assert ora.pair_kernel(ora.K_ATTREP, 3, a, [2.0, 0, 0])[0] < 0
+    # every kernel is odd with K(0) = 0
+    rng = np.random.default_rng(0)
+    for kern, d, a in ((ora.K_GAUSS, 2, 0.0), (ora.K_SOFTCOULOMB, 1, 1e-6), (ora.K_ATTREP, 3, 0.01)):
+        assert np.all(ora.pair_kernel(kern, d, a, np.zeros(d)) == 0.0)
+        for _ in range(20):
+            x = rng.standard_normal(d)
+            np.testing.assert_array_equal(ora.pair_kernel(kern, d, a, -x), -ora.pair_kernel(kern, d, a, x))
+
+
+# --------------------------------------------------------------------------
+# the random division (Sec. 2.1) and Lemma 3.1
+# --------------------------------------------------------------------------
+
+def test_permutation_is_key_order(ora):
+    prm = ora.Params(d=1, kernel=ora.K_GAUSS, kparam=0.0, beta=0.0, sigma=0.0, dt=1e-3, seed=3)
+    n = 1000
+    rng = np.random.default_rng(1)
+    slots = rng.permutation(n).astype(np.uint32)
+    perm = ora.permutation(prm, 17, slots)
+    assert sorted(perm.tolist()) == list(range(n))
+    pos = {int(pid): k for k, pid in enumerate(slots)}
+    keys = [(ora.perm_word(3, 0, 17, pos[int(pid)]) << 32) | int(pid) for pid in perm]
+    assert all(a < b for a, b in zip(keys, keys[1:]))
+
+
+@pytest.mark.parametrize("n,p", [(6, 2), (8, 4), (7, 3), (5, 2)])
+def test_division_law_is_uniform(ora, n, p):
+    """Every division is equally likely (M(n) of them when p | N, Lemma 3.1's
+    count), chaining the slot order from step to step as the method does."""
+    prm = ora.Params(d=1, kernel=ora.K_GAUSS, kparam=0.0, beta=0.0, sigma=0.0, dt=1e-3, seed=11)
+    allv = sorted({tuple(sorted(tuple(sorted(b)) for b in dv)) for dv in divisions(n, p)})
+    if n % p == 0:
+        assert len(allv) == M(n, p)
+    index = {v: k for k, v in enumerate(allv)}
+    steps = 2000 * len(allv)
+    counts = np.zeros(len(allv))
+    slots = np.arange(n, dtype=np.uint32)
+    for m in range(steps):
+        slots = ora.permutation(prm, m, slots)
+        counts[index[canon(slots.tolist(), p)]] += 1
+    assert stats.chisquare(counts).pvalue > 1e-4
+
+
+def test_consecutive_divisions_are_independent(ora):
+    prm = ora.Params(d=1, kernel=ora.K_GAUSS, kparam=0.0, beta=0.0, sigma=0.0, dt=1e-3, seed=5)
+    n, p = 4, 2
+    allv = sorted({canon(list(q), p) for q in itertools.permutations(range(n))})
+    index = {v: k for k, v in enumerate(allv)}
+    joint = np.zeros((3, 3))
+    slots = np.arange(n, dtype=np.uint32)
+    prev = None
+    for m in range(30000):
+        slots = ora.permutation(prm, m, slots)
+        cur = index[canon(slots.tolist(), p)]
+        if prev is not None:
+            joint[prev, cur] += 1
+        prev = cur
+    assert stats.chisquare(joint.ravel()).pvalue > 1e-4
+
+
+def test_pair_probability(ora):
+    """P(i, j in one batch) = (p-1)/(N-1) (proof of Lemma 3.1)."""
+    prm = ora.Params(d=1, kernel=ora.K_GAUSS, kparam=0.0, beta=0.0, sigma=0.0, dt=1e-3, seed=2)
+    n, p, steps = 64, 4, 4000
+    co = np.zeros((n, n))
+    slots = np.arange(n, dtype=np.uint32)
+    for m in range(steps):
+        slots = ora.permutation(prm, m, slots)
+        for q in range(n // p):
+            b = slots[q * p:(q + 1) * p]
+            co[np.ix_(b, b)] += 1
+    e = steps * (p - 1) / (n - 1)
+    sd = math.sqrt(steps * (p - 1) / (n - 1) * (1 - (p - 1) / (n - 1)))
+    off = co[~np.eye(n, dtype=bool)]
+    assert np.max(np.abs(off - e)) < 5.5 * sd
+    chi = np.sum((off[: off.size // 2] - e) ** 2 / e)
+    assert stats.chi2.sf(chi, off.size // 2) > 1e-4
+
+
+CASES = [(6, 2, 0, 2), (6, 3, 2, 3), (8, 4, 1, 1), (8, 2, 0, 2), (7, 3, 2, 3), (7, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("n,p,kern,d", CASES)
+def test_lemma_3_1_exactly(ora, n, p, kern, d):
+    """Over all divisions: mean of the batch force = direct force, and when
+    p | N the variance is (1/(p-1) - 1/(N-1)) Lambda_i (Lemma 3.1)."""
+    a = {0: 0.0, 1: 0.5, 2: 0.01}[kern]
+    prm = ora.Params(d=d, kernel=kern, kparam=a, beta=1.0, sigma=0.0, dt=1e-3)
+    x = rbm_inputs.normal(n, d, seed=n * 10 + p).astype(np.float64)
+    fd = ora.direct_forces(prm, x)
+    fs = []
+    for dv in divisions(n, p):
+        perm = np.array([i for b in dv for i in b], np.uint32)
+        fs.append(ora.rbm_forces(prm, p, x, perm))
+    fs = np.array(fs)
+    scale = np.max(np.abs(fd)) + 1.0
+    np.testing.assert_allclose(fs.mean(axis=0), fd, rtol=0, atol=1e-13 * scale)
+    if n % p == 0:
+        var = np.mean(np.sum((fs - fd[None]) ** 2, axis=2), axis=0)
+        lam = np.zeros(n)
+        for i in range(n):
+            kij = np.array([ora.pair_kernel(kern, d, a, x[i] - x[j]) for j in range(n) if j != i])
+            lam[i] = np.sum(np.sum((kij - kij.mean(axis=0)) ** 2, axis=1)) / (n - 2)
+        pred = (1.0 / (p - 1) - 1.0 / (n - 1)) * lam
+        np.testing.assert_allclose(var, pred, rtol=1e-11, atol=1e-14)
+
+
+def test_single_batch_is_the_direct_sum(ora):
+    """p = N: one batch, so the RBM force and step are the full system's."""
+    n, d = 50, 2
+    prm = ora.Params(d=d, kernel=ora.K_GAUSS, kparam=0.0, beta=1.0, sigma=0.5, dt=1e-3, seed=1)
+    x = rbm_inputs.normal(n, d, seed=4)
+    perm = ora.permutation(prm, 0, np.arange(n))
+    np.testing.assert_allclose(ora.rbm_forces(prm, n, x, perm), ora.direct_forces(prm, x), rtol=1e-12, atol=1e-15)
+    x1, _ = ora.rbm_step(prm, n, 0, x, np.arange(n))
+    np.testing.assert_allclose(x1, ora.direct_step(prm, 0, x), rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# the update: exact linear identities
+# --------------------------------------------------------------------------
+
+def test_odd_kernel_conserves_the_mean(ora):
+    """Odd K: forces cancel inside each batch, so with V = 0 and sigma = 0
+    the centre of mass never moves; with V = |x|^2/2 it contracts by
+    (1 - dt); with noise it moves by sigma sqrt(dt) mean(z)."""
+    n, d = 1000, 3
+    x0 = rbm_inputs.normal(n, d, seed=8).astype(np.float64) + 0.3
+    prm = ora.Params(d=d, kernel=ora.K_ATTREP, kparam=0.01, beta=0.0, sigma=0.0, dt=1e-3)
+    x, _ = ora.rbm_run(prm, 7, 0, 50, x0)
+    np.testing.assert_allclose(x.mean(axis=0), x0.mean(axis=0), rtol=0, atol=1e-13)
+    prm.beta = 1.0
+    x, _ = ora.rbm_run(prm, 7, 0, 50, x0)
+    np.testing.assert_allclose(x.mean(axis=0), (1 - 1e-3) ** 50 * x0.mean(axis=0), rtol=1e-12)
+    prm.sigma = 0.1
+    x1, _ = ora.rbm_step(prm, 7, 3, x0, np.arange(n))
+    z = np.array([ora.normals(prm.seed, 0, 3, i)[:d] for i in range(n)])
+    want = (1 - 1e-3) * x0.mean(axis=0) + 0.1 * math.sqrt(1e-3) * z.mean(axis=0)
+    np.testing.assert_allclose(x1.mean(axis=0), want, rtol=0, atol=1e-14)
+
+
+def test_second_moment_step_identity(ora):
+    """d = 1, V = x^2/2, sigma = 0: X' = (1-dt) X + dt F, hence
+    m2' = (1-dt)^2 m2 + 2 dt (1-dt) mean(xF) + dt^2 mean(F^2).  For p = 2 and
+    K = 1/x the pair identity x_i K(x_i-x_j) + x_j K(x_j-x_i) = 1 gives
+    mean(xF) = 1/2 exactly."""
+    n, dt = 4096, 1e-3
+    x = rbm_inputs.uniform(n, 1, -3, 3, seed=2).astype(np.float64)
+    prm = ora.Params(d=1, kernel=ora.K_SOFTCOULOMB, kparam=0.0, beta=1.0, sigma=0.0, dt=dt, seed=1)
+    slots = np.arange(n)
+    perm = ora.permutation(prm, 0, slots)
+    f = ora.rbm_forces(prm, 2, x, perm)
+    assert np.mean(x * f) == pytest.approx(0.5, rel=1e-12)
+    x1, _ = ora.rbm_step(prm, 2, 0, x, slots)
+    m2, c1, c2 = np.mean(x ** 2), np.mean(x * f), np.mean(f ** 2)
+    assert np.mean(x1 ** 2) == pytest.approx((1 - dt) ** 2 * m2 + 2 * dt * (1 - dt) * c1 + dt * dt * c2, rel=1e-12)
+
+
+def test_resume_from_saved_slots(ora):
+    """A run continued from (x, slot order, step index) equals the
+    uninterrupted run bit for bit: every random number is a function of
+    (seed, step, slot/id)."""
+    n, d = 300, 2
+    prm = ora.Params(d=d, kernel=ora.K_GAUSS, kparam=0.0, beta=1.0, sigma=0.5, dt=1e-3, seed=1)
+    x0 = rbm_inputs.normal(n, d)
+    xa, sa = ora.rbm_run(prm, 3, 0, 20, x0)
+    xh, sh = ora.rbm_run(prm, 3, 0, 10, x0)
+    xb, sb = ora.rbm_run(prm, 3, 10, 10, xh, sh)
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(sa, sb)
+
+
+# --------------------------------------------------------------------------
+# whole runs against the paper's rates and closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_error_decays_like_sqrt_tau(ora):
+    """Sec. 4.1 / Theorem 3.1: with K = x/(1+x^2), V = x^2/2, p = 2 and the
+    semicircle initial law of radius 2, the error (the RMS over particles of
+    Sec. 4.1) against the fully coupled system at T = 1 falls like tau^(1/2)."""
+    n = 256
+    x0 = rbm_inputs.semicircle(n, 2.0, seed=3).astype(np.float64)
+    ref_prm = ora.Params(d=1, kernel=ora.K_SOFTCOULOMB, kparam=1.0, beta=1.0, sigma=0.0, dt=2.0 ** -12)
+    xr = x0.copy()
+    for m in range(2 ** 12):
+        xr = ora.direct_step(ref_prm, m, xr)
+    taus = [2.0 ** -k for k in (4, 5, 6, 7, 8)]
+    errs = []
+    for tau in taus:
+        e2 = []
+        for seed in range(1, 9):
+            prm = ora.Params(d=1, kernel=ora.K_SOFTCOULOMB, kparam=1.0, beta=1.0, sigma=0.0, dt=tau, seed=seed)
+            x, _ = ora.rbm_run(prm, 2, 0, int(round(1.0 / tau)), x0)
+            e2.append(ora.rms_error(x, xr) ** 2)
+        errs.append(math.sqrt(np.mean(e2)))
+    slope = np.polyfit(np.log(taus), np.log(errs), 1)[0]
+    assert 0.4 < slope < 0.62, (slope, errs)
+
+
+@pytest.mark.slow
+def test_softened_coulomb_relaxes_to_the_semicircle(ora):
+    """Sec. 4.2: with V = x^2/2 and the Coulomb-like kernel, the empirical
+    law relaxes to the semicircle rho = sqrt(2 - x^2)/pi; for p = 2 the pair
+    identity makes m2(t) = 1/2 + (m2(0) - 1/2) e^{-2t} in the limit of no
+    softening."""
+    n, dt, a = 8192, 1e-3, 0.05 ** 2
+    x0 = rbm_inputs.uniform(n, 1, -3, 3, seed=1).astype(np.float64)
+    prm = ora.Params(d=1, kernel=ora.K_SOFTCOULOMB, kparam=a, beta=1.0, sigma=0.0, dt=dt, seed=1)
+    m20 = float(np.mean(x0 ** 2))
+    x, slots = ora.rbm_run(prm, 2, 0, 500, x0)
+    want = 0.5 + (m20 - 0.5) * math.exp(-1.0)
+    assert float(np.mean(x ** 2)) == pytest.approx(want, rel=0.03)
+    x, slots = ora.rbm_run(prm, 2, 500, 3500, x, slots)
+    assert ora.ks_distance(x, ora.semicircle_cdf) < 0.02
+    # At equilibrium m2 sits at the fixed point of the exact step identity,
+    # m2* = [2 (1-dt) c1 + dt c2] / (2 - dt), with c1 = mean(xF) and
+    # c2 = mean(F^2) averaged over steps; softening makes c1 < 1/2.
+    c1, c2 = [], []
+    for m in range(4000, 4200):
+        perm = ora.permutation(prm, m, slots)
+        f = ora.rbm_forces(prm, 2, x, perm)
+        c1.append(np.mean(x * f))
+        c2.append(np.mean(f * f))
+        x, slots = ora.rbm_step(prm, 2, m, x, slots)
+    m2s = (2 * (1 - dt) * np.mean(c1) + dt * np.mean(c2)) / (2 - dt)
+    assert float(np.mean(x ** 2)) == pytest.approx(m2s, abs=0.005)
+    assert 0.45 < m2s < 0.5
