@@ -1,0 +1,169 @@
+/*
+ * rbm.h -- C ABI of librbm.so: the Random Batch Method RBM-1 (Jin, Li & Liu,
+ * arXiv:1812.10575, Sec. 2.1, Algorithm 1) for the binary interacting
+ * particle system of eq. (1.2),
+ *
+ *     dX^i = -grad V(X^i) dt + 1/(N-1) sum_{j != i} K(X^i - X^j) dt + sigma dB^i,
+ *
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *     never allocates, frees or retains device memory beyond the workspace
+ *     the caller hands to rbm_init (which must outlive the context).
+ *   - Positions at the boundary are FP32, row-major [N][d], indexed by
+ *     particle id 0..N-1.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work on it; nothing is waited for unless stated.
+ *   - Argument errors are detected before anything is enqueued and return
+ *     RBM_ERR_INVALID / RBM_ERR_UNSUPPORTED / RBM_ERR_WORKSPACE.  HIP launch
+ *     failures return RBM_ERR_HIP.  rbm_last_error() returns a thread-local
+ *     description of the last failure.  No call aborts or throws.
+ *
+ * Random numbers (the paper leaves the source open; this library fixes it):
+ *   Philox4x32-10 (Salmon et al., SC'11) with key (seed lo32, seed hi32).
+ *   PERM word of slot k at step m : Philox(ctr = (k>>2, m, 0, sys))[k & 3]
+ *   NOISE of particle i at step m : Philox(ctr = (i, m, 1, sys)), 4 words ->
+ *       uniforms u = (2 (w >> 9) + 1) 2^-24 -> Box-Muller pairs (u0,u1), (u2,u3)
+ *   Step m orders the particles by the 64-bit key (PERM word of its slot << 32
+ *   | id); rank r in that order is the particle's slot at step m+1; the
+ *   batches of step m are ranks [qp, qp+p), the last of the floor(N/p)
+ *   batches also taking the N mod p leftover ranks.
+ */
+#ifndef RBM_H
+#define RBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RBM_OK = 0,
+    RBM_ERR_INVALID = 1,     /* bad argument (null pointer, out-of-range value) */
+    RBM_ERR_WORKSPACE = 2,   /* workspace too small or misaligned */
+    RBM_ERR_HIP = 3,         /* a HIP runtime call failed */
+    RBM_ERR_UNSUPPORTED = 4, /* valid but outside what the kernels implement */
+    RBM_ERR_DEVICE = 5       /* a device-side check failed (see rbm_check) */
+} rbm_status;
+
+/* Interaction kernels K of eq. (1.2); a = rbm_params.kparam.
+ *   RBM_K_GAUSS       K(x) = -x exp(-|x|^2)
+ *   RBM_K_SOFTCOULOMB K(x) = x / (|x|^2 + a)   (a = 1: the kernel of Sec. 4.1;
+ *                                               small a: softened 1/x of Sec. 4.2)
+ *   RBM_K_ATTREP      K(x) = x / (|x|^2 + a) - x                              */
+typedef enum { RBM_K_GAUSS = 0, RBM_K_SOFTCOULOMB = 1, RBM_K_ATTREP = 2 } rbm_kernel;
+
+/* Model, method and stream parameters.  V(x) = beta |x|^2 / 2. */
+typedef struct {
+    int32_t d;        /* space dimension, 1..3 */
+    int32_t kernel;   /* rbm_kernel */
+    int64_t n;        /* particles N, 2 <= N <= RBM_MAX_N */
+    int32_t p;        /* batch size, 2 <= p <= N (p <= RBM_MAX_P_MULTI when N > one bucket) */
+    int32_t reserved; /* must be 0 */
+    double kparam;    /* kernel softening a >= 0 */
+    double beta;      /* external field coefficient: -grad V(x) = -beta x */
+    double sigma;     /* noise amplitude sigma >= 0 */
+    double dt;        /* time step tau > 0 */
+    uint64_t seed;    /* Philox key */
+    uint32_t sys;     /* Philox counter word 3 (system index in an ensemble) */
+    uint32_t reserved2; /* must be 0 */
+} rbm_params;
+
+#define RBM_MAX_N (1LL << 25)
+#define RBM_MAX_P_MULTI 64
+
+typedef struct rbm_ctx rbm_ctx;
+
+/* Bytes of device workspace rbm_init needs for these parameters. */
+rbm_status rbm_workspace_size(const rbm_params *prm, size_t *bytes);
+
+/* Create a context.  d_x0: [N][d] FP32 positions by id.  d_slots: NULL for
+ * the identity slot order, else N distinct ids (uint32) giving the id in
+ * each slot (the value rbm_perm returns; used to resume a run).  step0: the
+ * index m of the first step rbm_step will take (0 <= step0 < 2^32).
+ * d_ws: workspace of ws_bytes >= rbm_workspace_size, 256-byte aligned.
+ * Enqueues the layout set-up on stream; *out is a host object freed by
+ * rbm_destroy. */
+rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_slots,
+                    int64_t step0, void *d_ws, size_t ws_bytes, void *stream,
+                    rbm_ctx **out);
+
+/* One RBM-1 step m -> m+1 (Algorithm 1): a fresh random division, batch
+ * forces 1/(s-1) sum_{j in batch} K(X_i - X_j) (eq. (2.3), s the batch size),
+ * forward Euler-Maruyama update X += dt (-beta X + F) + sigma sqrt(dt) z. */
+rbm_status rbm_step(rbm_ctx *ctx, void *stream);
+
+/* nsteps consecutive rbm_step calls (bitwise identical to calling rbm_step
+ * nsteps times). */
+rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream);
+
+/* Current positions, [N][d] FP32 by id. */
+rbm_status rbm_positions(rbm_ctx *ctx, float *d_x, void *stream);
+
+/* Current slot order: d_ids[k] = id of the particle in slot k (N uint32).
+ * After a step this is that step's permutation (ids in key order). */
+rbm_status rbm_perm(rbm_ctx *ctx, uint32_t *d_ids, void *stream);
+
+/* Batch forces F_i (eq. (2.3)) of the division that step index `step` would
+ * draw from the current slot order, at the current positions; [N][d] FP32 by
+ * id.  The state is not changed. */
+rbm_status rbm_forces(rbm_ctx *ctx, int64_t step, float *d_f, void *stream);
+
+/* Index m of the next step. */
+rbm_status rbm_step_index(const rbm_ctx *ctx, int64_t *m);
+
+/* Wait for the stream and report device-side checks (a bucket larger than
+ * the on-chip capacity, which has probability far below 1e-30 per step for
+ * the supported sizes; a slot id >= N given to rbm_init): RBM_OK or
+ * RBM_ERR_DEVICE. */
+rbm_status rbm_check(rbm_ctx *ctx, void *stream);
+
+/* Kernel phases of one step, for rbm_phase_times. */
+enum {
+    RBM_PHASE_COUNT = 0,   /* PERM words per (tile, bucket) */
+    RBM_PHASE_COLSCAN = 1, /* prefix over tiles per bucket */
+    RBM_PHASE_STARTS = 2,  /* bucket starts */
+    RBM_PHASE_SCATTER = 3, /* records to their buckets */
+    RBM_PHASE_SORT = 4,    /* in-LDS sort + batch force + update */
+    RBM_PHASE_FIXUP = 5,   /* batches cut by bucket boundaries */
+    RBM_NPHASES = 6
+};
+
+/* Measurement aid: with max_steps > 0, the next max_steps steps taken by
+ * rbm_step / rbm_run record a HIP event between consecutive kernels on the
+ * stream they run on (events are host-side objects; no device memory).
+ * max_steps = 0 stops recording and releases the events. */
+rbm_status rbm_timing(rbm_ctx *ctx, int32_t max_steps);
+
+/* Wait for the recorded steps and return, per phase, the mean milliseconds
+ * per step (ms[RBM_NPHASES]) over the *steps recorded steps; recording
+ * restarts from zero afterwards. */
+rbm_status rbm_phase_times(rbm_ctx *ctx, double *ms, int64_t *steps);
+
+/* Free the host context (not the workspace). */
+rbm_status rbm_destroy(rbm_ctx *ctx);
+
+/* Exact interaction force of eq. (1.2), F_i = 1/(N-1) sum_{j != i}
+ * K(X_i - X_j), for the nids particles listed in d_ids (NULL: all N, in id
+ * order).  d_x: [N][d] by id; d_f: [nids][d].  FP32 pair terms, FP64 sums. */
+rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t *d_ids,
+                         int64_t nids, float *d_f, void *stream);
+
+/* One step of the fully coupled system with the update and NOISE stream of
+ * RBM-1 step `step`: d_x_out = d_x + dt (-beta d_x + F) + sigma sqrt(dt) z.
+ * d_x_out must not alias d_x. */
+rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out,
+                       int64_t step, void *stream);
+
+/* Text of a status code, and the last error of this thread. */
+const char *rbm_status_str(rbm_status st);
+const char *rbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBM_H */

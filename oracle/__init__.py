@@ -200,7 +200,8 @@ def direct_step(prm: Params, m: int, x) -> np.ndarray:
 def semicircle_cdf(x):
     """CDF of the semicircle law rho(x) = sqrt(2 - x^2) / pi (Sec. 4.2)."""
     x = np.clip(np.asarray(x, np.float64), -math.sqrt(2.0), math.sqrt(2.0))
-    return 0.5 + x * np.sqrt(2.0 - x * x) / (2.0 * math.pi) + np.arcsin(x / math.sqrt(2.0)) / math.pi
+    r = np.sqrt(np.maximum(2.0 - x * x, 0.0))
+    return 0.5 + x * r / (2.0 * math.pi) + np.arcsin(np.clip(x / math.sqrt(2.0), -1.0, 1.0)) / math.pi
 
 
 def ks_distance(samples, cdf) -> float:

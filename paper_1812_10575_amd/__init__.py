@@ -1,0 +1,266 @@
+"""Python binding of librbm.so: the RBM-1 step (arXiv:1812.10575, Sec. 2.1,
+Algorithm 1) on an AMD Instinct MI355X.
+
+Every function here has the name of a C entry point of ``include/rbm.h`` and
+only marshals arguments: torch tensors supply device memory and the current
+HIP stream, every step of the method runs in the library's HIP kernels.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbm.so")
+
+RBM_OK, RBM_ERR_INVALID, RBM_ERR_WORKSPACE, RBM_ERR_HIP, RBM_ERR_UNSUPPORTED, RBM_ERR_DEVICE = range(6)
+RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP = 0, 1, 2
+RBM_MAX_N = 1 << 25
+RBM_MAX_P_MULTI = 64
+
+# every symbol the header declares
+SYMBOLS = (
+    "rbm_workspace_size", "rbm_init", "rbm_step", "rbm_run", "rbm_positions", "rbm_perm",
+    "rbm_forces", "rbm_step_index", "rbm_check", "rbm_timing", "rbm_phase_times", "rbm_destroy",
+    "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
+)
+PHASES = ("count", "colscan", "starts", "scatter", "sort", "fixup")
+
+
+class RbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class rbm_params(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("kernel", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("p", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kparam", ctypes.c_double),
+                ("beta", ctypes.c_double), ("sigma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("sys", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1812_10575_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    pp = ctypes.POINTER(rbm_params)
+    sig = {
+        "rbm_workspace_size": [pp, ctypes.POINTER(sz)],
+        "rbm_init": [pp, vp, vp, i64, vp, sz, vp, ctypes.POINTER(vp)],
+        "rbm_step": [vp, vp],
+        "rbm_run": [vp, i64, vp],
+        "rbm_positions": [vp, vp, vp],
+        "rbm_perm": [vp, vp, vp],
+        "rbm_forces": [vp, i64, vp, vp],
+        "rbm_step_index": [vp, ctypes.POINTER(i64)],
+        "rbm_check": [vp, vp],
+        "rbm_timing": [vp, ctypes.c_int32],
+        "rbm_phase_times": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+        "rbm_destroy": [vp],
+        "direct_forces": [pp, vp, vp, i64, vp, vp],
+        "direct_step": [pp, vp, vp, i64, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.rbm_status_str.argtypes = [ctypes.c_int]
+    L.rbm_status_str.restype = ctypes.c_char_p
+    L.rbm_last_error.argtypes = []
+    L.rbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != RBM_OK:
+        L = lib()
+        raise RbmError(st, f"{L.rbm_status_str(st).decode()}: {L.rbm_last_error().decode()}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Params:
+    """Parameters of eq. (1.2) with V = beta |x|^2 / 2 and of RBM-1."""
+    d: int
+    kernel: int
+    n: int
+    p: int
+    kparam: float = 0.0
+    beta: float = 0.0
+    sigma: float = 0.0
+    dt: float = 1e-3
+    seed: int = 1
+    sys: int = 0
+
+    def c(self) -> rbm_params:
+        return rbm_params(self.d, self.kernel, self.n, self.p, 0, self.kparam, self.beta,
+                          self.sigma, self.dt, self.seed, self.sys, 0)
+
+
+# --------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# --------------------------------------------------------------------------
+
+def rbm_status_str(st: int) -> str:
+    return lib().rbm_status_str(st).decode()
+
+
+def rbm_last_error() -> str:
+    return lib().rbm_last_error().decode()
+
+
+def rbm_workspace_size(prm: Params) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().rbm_workspace_size(ctypes.byref(prm.c()), ctypes.byref(n)))
+    return n.value
+
+
+def rbm_init(prm: Params, x0, slots=None, step0: int = 0, ws=None, stream=None) -> "Context":
+    """Create a context on x0 ([N][d] float32 CUDA tensor, by id)."""
+    import torch
+    _expect(x0, torch.float32, (prm.n, prm.d), "x0")
+    if slots is not None:
+        _expect(slots, torch.int32, (prm.n,), "slots")
+    nbytes = rbm_workspace_size(prm)
+    if ws is None:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=x0.device)
+    base = (ws.data_ptr() + 255) & ~255
+    avail = ws.numel() - (base - ws.data_ptr())
+    h = ctypes.c_void_p()
+    cp = prm.c()
+    _check(lib().rbm_init(ctypes.byref(cp), _ptr(x0), _ptr(slots), step0, ctypes.c_void_p(base),
+                          avail, _stream(stream), ctypes.byref(h)))
+    return Context(prm, h, ws)
+
+
+def rbm_step(ctx: "Context", stream=None):
+    _check(lib().rbm_step(ctx.handle, _stream(stream)))
+
+
+def rbm_run(ctx: "Context", nsteps: int, stream=None):
+    _check(lib().rbm_run(ctx.handle, nsteps, _stream(stream)))
+
+
+def rbm_positions(ctx: "Context", out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((ctx.prm.n, ctx.prm.d), dtype=torch.float32, device=ctx.ws.device)
+    _expect(out, torch.float32, (ctx.prm.n, ctx.prm.d), "out")
+    _check(lib().rbm_positions(ctx.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def rbm_perm(ctx: "Context", out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(ctx.prm.n, dtype=torch.int32, device=ctx.ws.device)
+    _expect(out, torch.int32, (ctx.prm.n,), "out")
+    _check(lib().rbm_perm(ctx.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def rbm_forces(ctx: "Context", step: int, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((ctx.prm.n, ctx.prm.d), dtype=torch.float32, device=ctx.ws.device)
+    _expect(out, torch.float32, (ctx.prm.n, ctx.prm.d), "out")
+    _check(lib().rbm_forces(ctx.handle, step, _ptr(out), _stream(stream)))
+    return out
+
+
+def rbm_step_index(ctx: "Context") -> int:
+    m = ctypes.c_int64()
+    _check(lib().rbm_step_index(ctx.handle, ctypes.byref(m)))
+    return m.value
+
+
+def rbm_check(ctx: "Context", stream=None):
+    _check(lib().rbm_check(ctx.handle, _stream(stream)))
+
+
+def rbm_timing(ctx: "Context", max_steps: int):
+    _check(lib().rbm_timing(ctx.handle, max_steps))
+
+
+def rbm_phase_times(ctx: "Context"):
+    """(dict phase -> mean ms per step, number of steps recorded)."""
+    ms = (ctypes.c_double * len(PHASES))()
+    n = ctypes.c_int64()
+    _check(lib().rbm_phase_times(ctx.handle, ms, ctypes.byref(n)))
+    return dict(zip(PHASES, list(ms))), n.value
+
+
+def rbm_destroy(ctx: "Context"):
+    if ctx.handle is not None:
+        _check(lib().rbm_destroy(ctx.handle))
+        ctx.handle = None
+
+
+def direct_forces(prm: Params, x, ids=None, out=None, stream=None):
+    import torch
+    _expect(x, torch.float32, (prm.n, prm.d), "x")
+    nids = prm.n if ids is None else ids.numel()
+    if ids is not None:
+        _expect(ids, torch.int32, (nids,), "ids")
+    if out is None:
+        out = torch.empty((nids, prm.d), dtype=torch.float32, device=x.device)
+    _expect(out, torch.float32, (nids, prm.d), "out")
+    _check(lib().direct_forces(ctypes.byref(prm.c()), _ptr(x), _ptr(ids), nids, _ptr(out),
+                               _stream(stream)))
+    return out
+
+
+def direct_step(prm: Params, x, step: int, out=None, stream=None):
+    import torch
+    _expect(x, torch.float32, (prm.n, prm.d), "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _expect(out, torch.float32, (prm.n, prm.d), "out")
+    _check(lib().direct_step(ctypes.byref(prm.c()), _ptr(x), _ptr(out), step, _stream(stream)))
+    return out
+
+
+def _expect(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name}: need a contiguous CUDA {dtype} tensor of shape {shape}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+@dataclass
+class Context:
+    """An RBM-1 run: host handle plus the workspace tensor that backs it."""
+    prm: Params
+    handle: ctypes.c_void_p
+    ws: object = field(repr=False)
+
+    def __del__(self):
+        try:
+            if self.handle is not None and _lib is not None:
+                _lib.rbm_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

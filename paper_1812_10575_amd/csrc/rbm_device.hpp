@@ -1,0 +1,163 @@
+// Device building blocks of the RBM-1 step for gfx950: the Philox4x32-10
+// counter-based generator, uniform and Gaussian transforms, particle records
+// and the pair kernels K of eq. (1.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rbm {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Ten rounds; each
+// multiplies counter words 0 and 2 by fixed odd constants, swaps the
+// product halves into place and mixes words 1, 3 and the key in by xor.  The
+// key advances by the two Weyl constants between rounds.  The key is uniform
+// across a wavefront, so its schedule stays in scalar registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, uint32_t j)
+{
+    return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// Stream words of the counter (word 2 of the counter selects the stream).
+enum : uint32_t { STREAM_PERM = 0u, STREAM_NOISE = 1u };
+
+// Uniform on (0,1) with 24 significant bits, so the value is exact in FP32:
+// (2 * (w >> 9) + 1) * 2^-24.
+__device__ __forceinline__ float u24(uint32_t w)
+{
+    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
+}
+
+// Box-Muller: two independent standard normals from two uniforms.
+__device__ __forceinline__ void box_muller(float u0, float u1, float &z0, float &z1)
+{
+    const float r = sqrtf(-2.0f * logf(u0));
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// D standard normals of particle `id` at step m: NOISE block (id, m, 1, sys),
+// pairs (u0,u1) and (u2,u3).  Only the pairs needed for D are evaluated.
+template <int D>
+__device__ __forceinline__ void noise(uint32_t id, uint32_t m, uint32_t sys, uint32_t k0,
+                                      uint32_t k1, float (&z)[D])
+{
+    const uint4 w = philox4x32_10(make_uint4(id, m, STREAM_NOISE, sys), k0, k1);
+    float a, b;
+    box_muller(u24(w.x), u24(w.y), a, b);
+    z[0] = a;
+    if constexpr (D >= 2) z[1] = b;
+    if constexpr (D >= 3) {
+        float c, e;
+        box_muller(u24(w.z), u24(w.w), c, e);
+        z[2] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Particle record: position and id travel together through the permuted
+// layouts.  d = 3 is one 16-byte vector.
+// ---------------------------------------------------------------------------
+template <int D> struct Rec;
+template <> struct alignas(8) Rec<1> { float x[1]; uint32_t id; };
+template <> struct Rec<2> { float x[2]; uint32_t id; };
+template <> struct alignas(16) Rec<3> { float x[3]; uint32_t id; };
+
+// ---------------------------------------------------------------------------
+// Pair kernels, written as K(x) = s(|x|^2) x:
+//   GAUSS       s = -exp(-r2)
+//   SOFTCOULOMB s = 1 / (r2 + a)
+//   ATTREP      s = 1 / (r2 + a) - 1
+// ---------------------------------------------------------------------------
+enum : int { K_GAUSS = 0, K_SOFTCOULOMB = 1, K_ATTREP = 2 };
+
+template <int KERN>
+__device__ __forceinline__ float pair_scale(float r2, float a)
+{
+    if constexpr (KERN == K_GAUSS) {
+        return -expf(-r2);
+    } else if constexpr (KERN == K_SOFTCOULOMB) {
+        return __builtin_amdgcn_rcpf(r2 + a);
+    } else {
+        return __builtin_amdgcn_rcpf(r2 + a) - 1.0f;
+    }
+}
+
+// acc += K(xi - xj)
+template <int D, int KERN>
+__device__ __forceinline__ void add_pair(const float (&xi)[D], const float *xj, float a,
+                                         float (&acc)[D])
+{
+    float dx[D];
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        dx[k] = xi[k] - xj[k];
+        r2 = fmaf(dx[k], dx[k], r2);
+    }
+    const float s = pair_scale<KERN>(r2, a);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] = fmaf(s, dx[k], acc[k]);
+}
+
+// Parameters of one step, passed by value to every kernel of the step.
+struct StepArgs {
+    uint32_t n;      // particles
+    uint32_t p;      // batch size
+    uint32_t nbat;   // floor(n / p) batches; the last takes the leftover
+    uint32_t m;      // step index (Philox counter word 1)
+    uint32_t k0, k1; // Philox key
+    uint32_t sys;    // Philox counter word 3
+    uint32_t nbuck;  // buckets of the key-space partition
+    float a;         // kernel softening
+    float beta;      // -grad V = -beta x
+    float dt;        // time step
+    float ssd;       // sigma * sqrt(dt)
+};
+
+// Batch [bs, be) of sorted rank r: groups of p, the last also takes the
+// n mod p leftover ranks.
+__device__ __forceinline__ void batch_of(const StepArgs &s, uint32_t r, uint32_t &bs, uint32_t &be)
+{
+    uint32_t q = r / s.p;
+    if (q > s.nbat - 1) q = s.nbat - 1;
+    bs = q * s.p;
+    be = (q == s.nbat - 1) ? s.n : bs + s.p;
+}
+
+// Forward Euler-Maruyama: x <- x + dt (-beta x + F) + sigma sqrt(dt) z.
+template <int D>
+__device__ __forceinline__ void em_update(const StepArgs &s, float (&x)[D], const float (&f)[D],
+                                          uint32_t id)
+{
+    float z[D];
+    if (s.ssd != 0.0f) {
+        noise<D>(id, s.m, s.sys, s.k0, s.k1, z);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) z[k] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = x[k] + s.dt * (-s.beta * x[k] + f[k]) + s.ssd * z[k];
+}
+
+}  // namespace rbm

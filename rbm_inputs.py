@@ -59,3 +59,26 @@ def workload(name: str, n: int, seed: int = 1) -> np.ndarray:
     if name == "semicircle":
         return semicircle(n, 2.0, seed)
     raise ValueError(f"unknown workload {name!r}")
+
+
+# Named workloads: model/method parameters and the initial law.  Kernel
+# codes: 0 Gaussian attraction -x exp(-|x|^2), 1 softened Coulomb
+# x/(|x|^2 + a), 2 attraction-repulsion x/(|x|^2 + a) - x.
+WORKLOADS = {
+    # 2-D Gaussian attraction in a harmonic trap, with noise
+    "gauss2d-n1024-p2": dict(d=2, kernel=0, n=1024, p=2, kparam=0.0, beta=1.0, sigma=0.5,
+                             dt=1e-3, seed=1, init="gauss2d", steps=1000),
+    # 1-D softened Coulomb (eps = 1e-3) in a harmonic trap, no noise
+    "dyson1d-n2^20-p2": dict(d=1, kernel=1, n=1 << 20, p=2, kparam=1e-6, beta=1.0, sigma=0.0,
+                             dt=1e-4, seed=1, init="dyson1d", steps=100000),
+    # 3-D attraction-repulsion, free space, weak noise
+    "attrep3d-n2^24-p8": dict(d=3, kernel=2, n=1 << 24, p=8, kparam=0.01, beta=0.0, sigma=0.1,
+                              dt=1e-3, seed=1, init="attrep3d", steps=100),
+}
+
+
+def params_of(name: str, **over) -> dict:
+    """Parameter dict of a named workload, with overrides."""
+    w = dict(WORKLOADS[name])
+    w.update(over)
+    return w

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point the header declares, and rejects bad arguments before anything
+is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1812_10575_amd as rbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "rbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    fns = header_functions()
+    for name in ("rbm_init", "rbm_step", "rbm_run", "direct_step", "direct_forces", "rbm_positions"):
+        assert name in fns
+    assert set(fns) == set(rbm.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = rbm.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+        assert hasattr(rbm, name), name  # binding has the same names
+
+
+def P(**kw):
+    base = dict(d=3, kernel=rbm.RBM_K_ATTREP, n=1 << 16, p=8, kparam=0.01, beta=0.0, sigma=0.1, dt=1e-3)
+    base.update(kw)
+    return rbm.Params(**base)
+
+
+def test_workspace_size_grows_with_n():
+    small = rbm.rbm_workspace_size(P(n=1000))
+    big = rbm.rbm_workspace_size(P(n=1 << 20))
+    assert 0 < small < big
+    # state + scratch + staging of 16-byte records at least
+    assert big >= 3 * 16 * (1 << 20)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(d=0), rbm.RBM_ERR_INVALID),
+    (dict(d=4), rbm.RBM_ERR_INVALID),
+    (dict(kernel=7), rbm.RBM_ERR_INVALID),
+    (dict(n=1, p=2), rbm.RBM_ERR_INVALID),
+    (dict(p=1), rbm.RBM_ERR_INVALID),
+    (dict(n=100, p=101), rbm.RBM_ERR_INVALID),
+    (dict(dt=0.0), rbm.RBM_ERR_INVALID),
+    (dict(dt=float("nan")), rbm.RBM_ERR_INVALID),
+    (dict(sigma=-1.0), rbm.RBM_ERR_INVALID),
+    (dict(kparam=-1.0), rbm.RBM_ERR_INVALID),
+    (dict(n=(1 << 25) + 1), rbm.RBM_ERR_UNSUPPORTED),
+    (dict(n=100000, p=65), rbm.RBM_ERR_UNSUPPORTED),
+])
+def test_bad_parameters_are_rejected(kw, status):
+    with pytest.raises(rbm.RbmError) as ei:
+        rbm.rbm_workspace_size(P(**kw))
+    assert ei.value.status == status
+    assert rbm.rbm_last_error()
+
+
+def test_large_p_is_fine_when_one_workgroup_holds_the_system():
+    assert rbm.rbm_workspace_size(P(n=2000, p=2000)) > 0
+
+
+def test_init_checks_before_enqueueing():
+    L = rbm.lib()
+    prm = P(n=4096).c()
+    need = ctypes.c_size_t()
+    assert L.rbm_workspace_size(ctypes.byref(prm), ctypes.byref(need)) == rbm.RBM_OK
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: every call below fails its checks first
+    assert L.rbm_init(ctypes.byref(prm), None, None, 0, fake, need.value, None, ctypes.byref(h)) == rbm.RBM_ERR_INVALID
+    assert L.rbm_init(ctypes.byref(prm), fake, None, 0, fake, need.value - 1, None, ctypes.byref(h)) == rbm.RBM_ERR_WORKSPACE
+    assert L.rbm_init(ctypes.byref(prm), fake, None, 0, ctypes.c_void_p(0x100010), need.value, None, ctypes.byref(h)) == rbm.RBM_ERR_WORKSPACE
+    assert L.rbm_init(ctypes.byref(prm), fake, None, -1, fake, need.value, None, ctypes.byref(h)) == rbm.RBM_ERR_INVALID
+    assert L.rbm_init(ctypes.byref(prm), fake, None, 1 << 32, fake, need.value, None, ctypes.byref(h)) == rbm.RBM_ERR_INVALID
+    assert L.rbm_step(None, None) == rbm.RBM_ERR_INVALID
+    assert L.rbm_run(None, 3, None) == rbm.RBM_ERR_INVALID
+    assert L.direct_step(ctypes.byref(prm), fake, fake, 0, None) == rbm.RBM_ERR_INVALID  # aliasing
+    assert L.direct_forces(ctypes.byref(prm), None, None, 0, fake, None) == rbm.RBM_ERR_INVALID
+
+
+def test_status_strings():
+    for st in range(6):
+        assert rbm.rbm_status_str(st)
+    assert rbm.rbm_status_str(99) == "unknown status"

@@ -367,3 +367,22 @@ def test_softened_coulomb_relaxes_to_the_semicircle(ora):
     m2s = (2 * (1 - dt) * np.mean(c1) + dt * np.mean(c2)) / (2 - dt)
     assert float(np.mean(x ** 2)) == pytest.approx(m2s, abs=0.005)
     assert 0.45 < m2s < 0.5
+
+
+def test_semicircle_cdf_closed_form(ora):
+    """F(-sqrt2) = 0, F(0) = 1/2, F(sqrt2) = 1 and F' = sqrt(2 - x^2)/pi
+    (Sec. 4.2), including points at and beyond the support edge."""
+    r2 = math.sqrt(2.0)
+    assert ora.semicircle_cdf(-r2) == pytest.approx(0.0, abs=1e-15)
+    assert ora.semicircle_cdf(0.0) == pytest.approx(0.5, abs=1e-15)
+    assert ora.semicircle_cdf(r2) == pytest.approx(1.0, abs=1e-15)
+    assert np.all(np.isfinite(ora.semicircle_cdf(np.array([-5.0, -r2, r2, 5.0, np.nextafter(r2, 9)]))))
+    xs = np.linspace(-1.3, 1.3, 27)
+    h = 1e-6
+    dens = (ora.semicircle_cdf(xs + h) - ora.semicircle_cdf(xs - h)) / (2 * h)
+    np.testing.assert_allclose(dens, np.sqrt(2 - xs ** 2) / math.pi, rtol=1e-7)
+    # total mass 1 and second moment 1/2
+    x = np.linspace(-r2, r2, 200001)
+    rho = np.sqrt(np.maximum(2 - x ** 2, 0)) / math.pi
+    assert np.trapezoid(rho, x) == pytest.approx(1.0, abs=1e-6)
+    assert np.trapezoid(x * x * rho, x) == pytest.approx(0.5, abs=1e-6)
