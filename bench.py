@@ -36,7 +36,7 @@ def phase_bytes(w: dict) -> dict:
     data."""
     rec = 4 * (w["d"] + 1)
     n = w["n"]
-    return {"scatter": 2 * rec * n, "sort": 2 * rec * n}
+    return {"scatter": 2 * rec * n, "split": 2 * rec * n, "sort": 2 * rec * n}
 
 
 def cpu_baseline(w: dict, x0) -> dict:

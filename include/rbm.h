@@ -121,15 +121,17 @@ rbm_status rbm_step_index(const rbm_ctx *ctx, int64_t *m);
  * RBM_ERR_DEVICE. */
 rbm_status rbm_check(rbm_ctx *ctx, void *stream);
 
-/* Kernel phases of one step, for rbm_phase_times. */
+/* Kernels of one step, for rbm_phase_times (a kernel a step does not need
+ * measures 0). */
 enum {
-    RBM_PHASE_COUNT = 0,   /* PERM words per (tile, bucket) */
-    RBM_PHASE_COLSCAN = 1, /* prefix over tiles per bucket */
-    RBM_PHASE_STARTS = 2,  /* bucket starts */
-    RBM_PHASE_SCATTER = 3, /* records to their buckets */
-    RBM_PHASE_SORT = 4,    /* in-LDS sort + batch force + update */
-    RBM_PHASE_FIXUP = 5,   /* batches cut by bucket boundaries */
-    RBM_NPHASES = 6
+    RBM_PHASE_KEYCOUNT = 0,  /* fine-bucket histogram of the PERM words per slot tile */
+    RBM_PHASE_KEYSUM = 1,    /* fine-bucket totals */
+    RBM_PHASE_KEYSTARTS = 2, /* bucket starts and run cursors */
+    RBM_PHASE_SCATTER = 3,   /* records to their coarse buckets */
+    RBM_PHASE_SPLIT = 4,     /* coarse buckets to fine buckets */
+    RBM_PHASE_SORT = 5,      /* in-LDS sort + batch force + update */
+    RBM_PHASE_FIXUP = 6,     /* batches cut by fine-bucket boundaries */
+    RBM_NPHASES = 7
 };
 
 /* Measurement aid: with max_steps > 0, the next max_steps steps taken by

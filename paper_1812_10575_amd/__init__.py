@@ -26,7 +26,7 @@ SYMBOLS = (
     "rbm_forces", "rbm_step_index", "rbm_check", "rbm_timing", "rbm_phase_times", "rbm_destroy",
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
 )
-PHASES = ("count", "colscan", "starts", "scatter", "sort", "fixup")
+PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
 
 class RbmError(RuntimeError):

@@ -15,6 +15,8 @@
 using rbm::Plan;
 using rbm::StepArgs;
 
+static_assert(rbm::RBM_NPH == RBM_NPHASES, "phase count of the kernels and the header differ");
+
 struct rbm_ctx {
     rbm_params prm;
     Plan plan;
@@ -72,9 +74,9 @@ rbm_status check_params(const rbm_params *prm)
     if (!(prm->kparam >= 0.0) || !std::isfinite(prm->kparam))
         return fail(RBM_ERR_INVALID, "kparam must be >= 0");
     if (!std::isfinite(prm->beta)) return fail(RBM_ERR_INVALID, "beta must be finite");
-    if (prm->n > RBM_SORT_CAP && prm->p > RBM_MAX_P_MULTI)
+    if (prm->n > RBM_SINGLE_CAP && prm->p > RBM_MAX_P_MULTI)
         return fail(RBM_ERR_UNSUPPORTED, "p = %d above %d needs N <= %d", prm->p, RBM_MAX_P_MULTI,
-                    RBM_SORT_CAP);
+                    RBM_SINGLE_CAP);
     return RBM_OK;
 }
 
@@ -87,30 +89,53 @@ Plan make_plan(const rbm_params *prm)
     pl.d = prm->d;
     pl.kernel = prm->kernel;
     pl.rec_bytes = (size_t)4 * (prm->d + 1);
-    if (pl.n <= RBM_SORT_CAP) {
-        pl.nbuck = 1;
-        pl.tile = 0;
-        pl.ntiles = 0;
+    if (pl.n <= RBM_SINGLE_CAP) {
+        pl.nbuck = pl.nb1 = 1;
     } else {
-        pl.nbuck = (pl.n + RBM_BUCKET_MEAN - 1) / RBM_BUCKET_MEAN;
-        uint32_t tile = (pl.n + 255) / 256;
-        tile = (tile + 3) & ~3u;
-        if (tile < 4096) tile = 4096;
-        pl.tile = tile;
-        pl.ntiles = (pl.n + tile - 1) / tile;
+        const uint32_t target = (pl.n + RBM_BUCKET_MEAN - 1) / RBM_BUCKET_MEAN;
+        const uint32_t per = 1u << RBM_SPLIT_SHIFT;
+        if (target <= per) {
+            pl.shift = 0;
+            pl.nb1 = pl.nbuck = target;
+        } else {
+            pl.shift = RBM_SPLIT_SHIFT;
+            pl.nb1 = (target + per - 1) / per;
+            pl.nbuck = pl.nb1 * per;
+            // chunks per coarse bucket: room for the mean plus 16 standard deviations
+            const double mean = (double)pl.n / pl.nb1;
+            pl.jmax = (uint32_t)std::ceil((mean + 16.0 * std::sqrt(mean) + 64.0) / RBM_CHUNK);
+        }
+        pl.ntiles = (pl.n + RBM_TILE - 1) / RBM_TILE;
+        // about 128 key-count tiles, a multiple of 4 slots each
+        uint32_t tf = (pl.n + 127) / 128;
+        tf = (tf + 4095) & ~4095u;
+        pl.tilef = tf < 16384 ? 16384 : tf;
+        pl.ntf = (pl.n + pl.tilef - 1) / pl.tilef;
     }
     size_t off = 0;
-    const size_t recs = align256((size_t)pl.n * pl.rec_bytes);
-    pl.off_state = off; off += recs;
-    pl.off_scratch = off; off += recs;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t recs = (size_t)pl.n * pl.rec_bytes;
+    pl.off_state = take(recs);
+    pl.off_scratch = take(recs);
     if (pl.nbuck > 1) {
-        pl.off_stage = off; off += recs;
-        pl.off_w = off; off += align256((size_t)pl.n * 4);
-        pl.off_cnt = off; off += align256((size_t)pl.ntiles * pl.nbuck * 4);
-        pl.off_tot = off; off += align256((size_t)pl.nbuck * 4);
-        pl.off_bstart = off; off += align256((size_t)(pl.nbuck + 1) * 4);
+        pl.off_stage1 = take(recs);
+        pl.off_w1 = take((size_t)pl.n * 4);
+        if (pl.shift > 0) {
+            pl.off_stage2 = take(recs);
+            pl.off_w2 = take((size_t)pl.n * 4);
+        }
+        pl.off_kcnt = take((size_t)pl.ntf * pl.nbuck * 4);
+        pl.off_ftot = take((size_t)pl.nbuck * 4);
+        pl.off_fstart = take((size_t)(pl.nbuck + 1) * 4);
+        pl.off_fcur = take((size_t)pl.nbuck * 4);
+        pl.off_cstart = take((size_t)(pl.nb1 + 1) * 4);
+        pl.off_ccur = take((size_t)pl.nb1 * 4);
     }
-    pl.off_flags = off; off += 256;
+    pl.off_flags = take(256);
     pl.total = off;
     return pl;
 }
@@ -126,6 +151,8 @@ StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m)
     s.k1 = (uint32_t)(prm->seed >> 32);
     s.sys = prm->sys;
     s.nbuck = pl.nbuck;
+    s.inv_p1 = (float)(1.0 / (double)(pl.p - 1));
+    s.inv_last = (float)(1.0 / (double)(pl.p + pl.n % pl.p - 1));
     s.a = (float)prm->kparam;
     s.beta = (float)prm->beta;
     s.dt = (float)prm->dt;
@@ -273,7 +300,7 @@ rbm_status rbm_check(rbm_ctx *ctx, void *stream)
                                   hipMemcpyDeviceToHost, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rbm_check");
-    if (flags & 1u) return fail(RBM_ERR_DEVICE, "a bucket exceeded the sort capacity (%d records)", RBM_SORT_CAP);
+    if (flags & 1u) return fail(RBM_ERR_DEVICE, "a bucket exceeded its capacity");
     if (flags & 2u) return fail(RBM_ERR_DEVICE, "rbm_init: a slot id was >= N");
     return RBM_OK;
 }

@@ -19,11 +19,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // 32x32 -> 64-bit products: one v_mad_u64_u32 each
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -45,14 +45,15 @@ __device__ __forceinline__ float u24(uint32_t w)
     return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
 }
 
-// Box-Muller: two independent standard normals from two uniforms.
+// Box-Muller: two independent standard normals from two uniforms,
+// r = sqrt(-2 ln u0), angle 2 pi u1.  The hardware sine and cosine take
+// their argument in revolutions, so sin(2 pi u1) is v_sin_f32(u1); the
+// hardware logarithm is base 2 (ln u = log2(u) ln 2).
 __device__ __forceinline__ void box_muller(float u0, float u1, float &z0, float &z1)
 {
-    const float r = sqrtf(-2.0f * logf(u0));
-    float s, c;
-    sincospif(2.0f * u1, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
 }
 
 // D standard normals of particle `id` at step m: NOISE block (id, m, 1, sys),
@@ -94,7 +95,7 @@ template <int KERN>
 __device__ __forceinline__ float pair_scale(float r2, float a)
 {
     if constexpr (KERN == K_GAUSS) {
-        return -expf(-r2);
+        return -__builtin_amdgcn_exp2f(-1.4426950408889634f * r2);  // -e^{-r2}
     } else if constexpr (KERN == K_SOFTCOULOMB) {
         return __builtin_amdgcn_rcpf(r2 + a);
     } else {
@@ -127,7 +128,9 @@ struct StepArgs {
     uint32_t m;      // step index (Philox counter word 1)
     uint32_t k0, k1; // Philox key
     uint32_t sys;    // Philox counter word 3
-    uint32_t nbuck;  // buckets of the key-space partition
+    uint32_t nbuck;  // fine buckets of the key-space partition
+    float inv_p1;    // 1 / (p - 1)
+    float inv_last;  // 1 / (s - 1) for the last batch, s = p + n mod p
     float a;         // kernel softening
     float beta;      // -grad V = -beta x
     float dt;        // time step

@@ -2,30 +2,33 @@
 // (eq. (1.2)) for gfx950.
 //
 // One step m, with the particles held as records (x, id) in "slot" order
-// (the order left by the previous step):
+// (the order left by the previous step).  Slot k draws the PERM word w_k; the
+// key (w_k << 32 | id) orders the particles.  The word range is cut into B
+// equal "fine buckets", f = floor(w B / 2^32) (about 1024 records each),
+// grouped 2^shift at a time into coarse buckets.
 //
-//   1. k_bucket_count   every slot k draws its PERM word w_k (one Philox
-//                       block feeds four consecutive slots) and counts, per
-//                       tile of slots, how many words fall in each of B
-//                       equal ranges of [0, 2^32) ("buckets").  No memory
-//                       is read: the words depend only on (seed, m, k).
-//   2. k_bucket_colscan for each bucket, exclusive prefix over tiles
-//      k_bucket_starts  exclusive prefix of the bucket totals
-//   3. k_bucket_scatter records move to their bucket's region (with w);
-//                       order inside a bucket is left free.
-//   4. k_sort_step      one workgroup per bucket: load the bucket into LDS,
-//                       order it by the unique key (w << 32 | id) with a
-//                       counting pass on the next bits of w plus a rank
-//                       fix inside the (tiny) sub-buckets, then evaluate
-//                       the batch forces of eq. (2.3) for every batch that
-//                       lies inside the bucket, apply the Euler-Maruyama
-//                       update and write the record at its sorted rank,
-//                       which is its slot for step m+1.
-//   5. k_fixup          the batches cut by a bucket boundary (at most one
-//                       per boundary), one workgroup each.
+//   k_key_count      per tile of slots, fine-bucket histogram of the words
+//                    (ALU only: the words depend on (seed, m, slot), not on
+//                    the state)
+//   k_key_colsum     fine-bucket totals
+//   k_key_starts     fine and coarse bucket starts, run cursors
+//   k_scatter_coarse a tile's 16K records, held in registers, go to their
+//                    coarse buckets; each (tile, bucket) run is reserved with
+//                    one atomic and written through an LDS reorder so that
+//                    lanes store to consecutive addresses
+//   k_split          each 16K-record chunk of a coarse bucket goes to its
+//                    fine buckets the same way
+//   k_sort_step      one workgroup per fine bucket: order it in LDS by the
+//                    unique key, evaluate the batch forces of eq. (2.3) for
+//                    every batch inside the bucket, apply the Euler-Maruyama
+//                    update, write each record at its sorted rank (its slot
+//                    for step m+1)
+//   k_fixup          the batches cut by a fine-bucket boundary
 //
-// When N fits one workgroup's LDS, steps 1-3 and 5 vanish: a single
-// workgroup sorts, steps and writes the whole system in place.
+// Records land in a run in whatever order the atomics give; the in-LDS sort
+// by the unique key makes the result independent of it.  Up to 128 fine
+// buckets the split level is skipped (shift = 0); when N fits one
+// workgroup's LDS a single workgroup does the whole step in place.
 #include "rbm_device.hpp"
 #include "rbm_plan.hpp"
 
@@ -83,125 +86,372 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t w, uint32_t nbuck)
     return __umulhi(w, nbuck);
 }
 
+__device__ __forceinline__ uint32_t fine_of(uint32_t w, uint32_t nbuck)
+{
+    return __umulhi(w, nbuck);
+}
+
+// Exclusive scan of a[0..nb), nb <= 256, by the first wavefront into out;
+// returns the total to that wavefront's lanes.
+__device__ __forceinline__ uint32_t wave0_exclusive_scan(const uint32_t *a, uint32_t *out, uint32_t nb)
+{
+    const uint32_t lane = threadIdx.x;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t i = lane * 4 + k;
+        v[k] = i < nb ? a[i] : 0u;
+        sum += v[k];
+    }
+    const uint32_t inc = wave_inclusive_scan(sum);
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t i = lane * 4 + k;
+        if (i < nb) out[i] = run;
+        run += v[k];
+    }
+    return __shfl(inc, 63, 64);
+}
+
 // ---------------------------------------------------------------------------
-// 1. counts of PERM words per (tile, bucket)
+// key counts: fine-bucket histogram of the PERM words, per tile of slots
 // ---------------------------------------------------------------------------
-template <int TPB>
-__global__ __launch_bounds__(TPB) void k_bucket_count(StepArgs s, uint32_t tile, uint32_t *cnt)
+constexpr uint32_t TILE = RBM_TILE;    // slots per coarse-scatter workgroup
+constexpr uint32_t CHUNK = RBM_CHUNK;  // records per split workgroup
+constexpr int LVL_TPB = 1024;          // 16 records per thread
+constexpr int LVL_P = 16;
+constexpr int LVL_NB = 256;            // largest digit count of a level
+
+__global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, uint32_t *cnt)
 {
     extern __shared__ uint32_t hist[];
     const uint32_t nb = s.nbuck;
-    for (uint32_t i = threadIdx.x; i < nb; i += TPB) hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * tile;
-    const uint32_t end = min(base + tile, s.n);
-    for (uint32_t k = base + 4 * threadIdx.x; k < end; k += 4 * TPB) {
+    const uint32_t base = blockIdx.x * tilef;
+    const uint32_t end = min(base + tilef, s.n);
+    for (uint32_t k = base + 4 * threadIdx.x; k < end; k += 4 * 1024) {
         const uint4 w = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
-        atomicAdd(&hist[bucket_of(w.x, nb)], 1u);
-        if (k + 1 < end) atomicAdd(&hist[bucket_of(w.y, nb)], 1u);
-        if (k + 2 < end) atomicAdd(&hist[bucket_of(w.z, nb)], 1u);
-        if (k + 3 < end) atomicAdd(&hist[bucket_of(w.w, nb)], 1u);
+        atomicAdd(&hist[fine_of(w.x, nb)], 1u);
+        if (k + 1 < end) atomicAdd(&hist[fine_of(w.y, nb)], 1u);
+        if (k + 2 < end) atomicAdd(&hist[fine_of(w.z, nb)], 1u);
+        if (k + 3 < end) atomicAdd(&hist[fine_of(w.w, nb)], 1u);
     }
     __syncthreads();
     uint32_t *row = cnt + (size_t)blockIdx.x * nb;
-    for (uint32_t i = threadIdx.x; i < nb; i += TPB) row[i] = hist[i];
+    for (uint32_t i = threadIdx.x; i < nb; i += 1024) row[i] = hist[i];
 }
 
-// ---------------------------------------------------------------------------
-// 2. prefix sums: per bucket over tiles, then over bucket totals
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bucket_colscan(uint32_t ntiles, uint32_t nbuck,
-                                                        uint32_t *cnt, uint32_t *tot)
+// ftot[f] = sum over tiles of cnt[t][f]
+__global__ __launch_bounds__(256) void k_key_colsum(uint32_t ntf, uint32_t nbuck,
+                                                    const uint32_t *__restrict__ cnt,
+                                                    uint32_t *__restrict__ ftot)
 {
-    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= nbuck) return;
-    uint32_t run = 0;
-    uint32_t t = 0;
-    for (; t + 4 <= ntiles; t += 4) {
-        const uint32_t v0 = cnt[(size_t)(t + 0) * nbuck + b];
-        const uint32_t v1 = cnt[(size_t)(t + 1) * nbuck + b];
-        const uint32_t v2 = cnt[(size_t)(t + 2) * nbuck + b];
-        const uint32_t v3 = cnt[(size_t)(t + 3) * nbuck + b];
-        cnt[(size_t)(t + 0) * nbuck + b] = run;
-        cnt[(size_t)(t + 1) * nbuck + b] = run + v0;
-        cnt[(size_t)(t + 2) * nbuck + b] = run + v0 + v1;
-        cnt[(size_t)(t + 3) * nbuck + b] = run + v0 + v1 + v2;
-        run += v0 + v1 + v2 + v3;
-    }
-    for (; t < ntiles; ++t) {
-        const uint32_t v = cnt[(size_t)t * nbuck + b];
-        cnt[(size_t)t * nbuck + b] = run;
-        run += v;
-    }
-    tot[b] = run;
+    const uint32_t f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= nbuck) return;
+    uint32_t sum = 0;
+    for (uint32_t t = 0; t < ntf; ++t) sum += cnt[(size_t)t * nbuck + f];
+    ftot[f] = sum;
 }
 
-// bstart[b] = sum of tot[0..b), bstart[nbuck] = N; flags bit 0 if a bucket
-// exceeds the sort kernel's capacity.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_bucket_starts(uint32_t nbuck, uint32_t cap,
-                                                        const uint32_t *tot, uint32_t *bstart,
-                                                        uint32_t *flags)
+// One workgroup: fine starts (fstart[nbuck] = N), coarse starts
+// cstart[c] = fstart[c << shift], and the run cursors of both levels.
+// flags bit 0: a fine bucket above the sort capacity or a coarse bucket
+// above ccap records.
+__global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb1, uint32_t shift,
+                                                     uint32_t n, uint32_t fcap, uint32_t ccap,
+                                                     const uint32_t *__restrict__ ftot,
+                                                     uint32_t *__restrict__ fstart,
+                                                     uint32_t *__restrict__ fcur,
+                                                     uint32_t *__restrict__ cstart,
+                                                     uint32_t *__restrict__ ccur,
+                                                     uint32_t *__restrict__ flags)
 {
-    constexpr int TPB = 1024, PER = 16;
+    constexpr int TPB = 1024, PER = RBM_MAX_FINE / TPB;
     __shared__ uint32_t a[TPB * PER];
     __shared__ uint32_t tmp[TPB / 64];
     bool over = false;
-    for (int i = threadIdx.x; i < TPB * PER; i += TPB) {
-        const uint32_t v = (uint32_t)i < nbuck ? tot[i] : 0u;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(TPB * PER); i += TPB) {
+        const uint32_t v = i < nbuck ? ftot[i] : 0u;
         a[i] = v;
-        over |= v > cap;
+        over |= v > fcap;
     }
     __syncthreads();
-    const uint32_t total = block_exclusive_scan<TPB, PER>(a, tmp);
-    for (uint32_t i = threadIdx.x; i < nbuck; i += TPB) bstart[i] = a[i];
-    if (threadIdx.x == 0) bstart[nbuck] = total;
+    block_exclusive_scan<TPB, PER>(a, tmp);
+    for (uint32_t i = threadIdx.x; i < nbuck; i += TPB) {
+        fstart[i] = a[i];
+        fcur[i] = a[i];
+    }
+    for (uint32_t c = threadIdx.x; c < nb1; c += TPB) {
+        const uint32_t c0 = a[c << shift];
+        const uint32_t c1 = c + 1 < nb1 ? a[(c + 1) << shift] : n;
+        cstart[c] = c0;
+        ccur[c] = c0;
+        over |= c1 - c0 > ccap;
+    }
+    if (threadIdx.x == 0) {
+        fstart[nbuck] = n;
+        cstart[nb1] = n;
+    }
     if (over) atomicOr(flags, 1u);
 }
 
 // ---------------------------------------------------------------------------
-// 3. bucket scatter
+// staged writes: a workgroup's 16K records (in registers) go to per-digit
+// runs.  Each digit's run is reserved once with one global atomic on the
+// digit's cursor; the records are then ordered by digit in LDS, 4096 at a
+// time, so that consecutive lanes store to consecutive addresses.
 // ---------------------------------------------------------------------------
-template <int D, int TPB>
-__global__ __launch_bounds__(TPB) void k_bucket_scatter(StepArgs s, uint32_t tile,
-                                                        const Rec<D> *__restrict__ state,
-                                                        Rec<D> *__restrict__ stage,
-                                                        uint32_t *__restrict__ wout,
-                                                        const uint32_t *__restrict__ cnt,
-                                                        const uint32_t *__restrict__ bstart)
+template <int D>
+struct StageLds {
+    Rec<D> rec[4 * LVL_TPB];
+    uint32_t w[4 * LVL_TPB];
+    uint16_t dig[4 * LVL_TPB];
+    uint32_t cnt[LVL_NB];   // round counts / tile counts
+    uint32_t start[LVL_NB]; // round starts
+    uint32_t gbase[LVL_NB]; // next global position of each digit
+};
+
+// digit(w) = (fine_of(w) >> shift) & mask
+template <int D>
+__device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const uint32_t (&rid)[LVL_P],
+                             const uint32_t (&w)[LVL_P], uint32_t nact, uint32_t nbuck,
+                             uint32_t shift, uint32_t mask, uint32_t ndig, uint32_t *gcur,
+                             Rec<D> *__restrict__ out, uint32_t *__restrict__ wout)
 {
-    extern __shared__ uint32_t cur[];
-    const uint32_t nb = s.nbuck;
-    const uint32_t *row = cnt + (size_t)blockIdx.x * nb;
-    for (uint32_t i = threadIdx.x; i < nb; i += TPB) cur[i] = bstart[i] + row[i];
+    const uint32_t tid = threadIdx.x;
+    // record k of this thread is active if k < nact (the caller orders them so)
+    for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.cnt[d] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * tile;
-    const uint32_t end = min(base + tile, s.n);
-    auto place = [&](const Rec<D> &r, uint32_t w) {
-        const uint32_t pos = atomicAdd(&cur[bucket_of(w, nb)], 1u);
-        stage[pos] = r;
-        wout[pos] = w;
-    };
-    for (uint32_t k = base + 4 * threadIdx.x; k < end; k += 4 * TPB) {
-        const uint4 w4 = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
-        if (k + 4 <= end) {
-            const Rec<D> r0 = state[k], r1 = state[k + 1], r2 = state[k + 2], r3 = state[k + 3];
-            place(r0, w4.x);
-            place(r1, w4.y);
-            place(r2, w4.z);
-            place(r3, w4.w);
-        } else {
-            for (uint32_t j = 0; k + j < end; ++j) place(state[k + j], word_of(w4, j));
+#pragma unroll
+    for (int k = 0; k < LVL_P; ++k)
+        if ((uint32_t)k < nact) atomicAdd(&L.cnt[(fine_of(w[k], nbuck) >> shift) & mask], 1u);
+    __syncthreads();
+    for (uint32_t d = tid; d < ndig; d += LVL_TPB)
+        L.gbase[d] = L.cnt[d] ? atomicAdd(&gcur[d], L.cnt[d]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < LVL_P / 4; ++r) {
+        for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.cnt[d] = 0;
+        __syncthreads();
+        uint32_t lr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * r + q;
+            lr[q] = (uint32_t)k < nact ? atomicAdd(&L.cnt[(fine_of(w[k], nbuck) >> shift) & mask], 1u) : 0u;
         }
+        __syncthreads();
+        uint32_t total = 0;
+        if (tid < 64) total = wave0_exclusive_scan(L.cnt, L.start, ndig);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * r + q;
+            if ((uint32_t)k < nact) {
+                const uint32_t d = (fine_of(w[k], nbuck) >> shift) & mask;
+                const uint32_t slot = L.start[d] + lr[q];
+                Rec<D> t;
+#pragma unroll
+                for (int c = 0; c < D; ++c) t.x[c] = rx[k][c];
+                t.id = rid[k];
+                L.rec[slot] = t;
+                L.w[slot] = w[k];
+                L.dig[slot] = (uint16_t)d;
+            }
+        }
+        __syncthreads();
+        const uint32_t rt = L.start[ndig - 1] + L.cnt[ndig - 1];
+        (void)total;
+        for (uint32_t i = tid; i < rt; i += LVL_TPB) {
+            const uint32_t d = L.dig[i];
+            const uint32_t g = L.gbase[d] + (i - L.start[d]);
+            out[g] = L.rec[i];
+            wout[g] = L.w[i];
+        }
+        __syncthreads();
+        for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.gbase[d] += L.cnt[d];
+        __syncthreads();
     }
 }
 
+// Coarse scatter: tile of 16K slots.  Thread t holds slots 4(t + 1024 g) + j.
+// Records of a partial last tile are packed so that the first nact of each
+// thread are the valid ones.
+template <int D>
+__global__ __launch_bounds__(LVL_TPB) void k_scatter_coarse(StepArgs s, uint32_t shift, uint32_t nb1,
+                                                            const Rec<D> *__restrict__ state,
+                                                            uint32_t *__restrict__ ccur,
+                                                            Rec<D> *__restrict__ stage,
+                                                            uint32_t *__restrict__ wout)
+{
+    __shared__ StageLds<D> L;
+    const uint32_t base = blockIdx.x * TILE;
+    const uint32_t end = min(base + TILE, s.n);
+    float rx[LVL_P][D];
+    uint32_t rid[LVL_P], w[LVL_P];
+    uint32_t nact = 0;
+#pragma unroll
+    for (int g = 0; g < LVL_P / 4; ++g) {
+        const uint32_t k = base + 4 * (threadIdx.x + g * LVL_TPB);
+        const uint4 w4 = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Rec<D> t{};
+            if (k + j < end) t = state[k + j];
+#pragma unroll
+            for (int c = 0; c < D; ++c) rx[4 * g + j][c] = t.x[c];
+            rid[4 * g + j] = t.id;
+            w[4 * g + j] = j == 0 ? w4.x : (j == 1 ? w4.y : (j == 2 ? w4.z : w4.w));
+        }
+        // slots are consecutive per thread and groups ascend, so the valid
+        // records are a prefix
+        nact += (k < end) ? min(4u, end - k) : 0u;
+    }
+    staged_write<D>(L, rx, rid, w, nact, s.nbuck, shift, 0xffffffffu, nb1, ccur, stage, wout);
+}
+
+// Split: chunk j of coarse bucket c (workgroup c * jmax + j) into the 2^shift
+// fine buckets of c.
+template <int D>
+__global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
+                                                   const uint32_t *__restrict__ cstart,
+                                                   const Rec<D> *__restrict__ in,
+                                                   const uint32_t *__restrict__ win,
+                                                   uint32_t *__restrict__ fcur,
+                                                   Rec<D> *__restrict__ out,
+                                                   uint32_t *__restrict__ wout)
+{
+    __shared__ StageLds<D> L;
+    const uint32_t c = blockIdx.x / jmax, j = blockIdx.x % jmax;
+    const uint32_t c0 = cstart[c], c1 = cstart[c + 1];
+    const uint32_t lo = min(c0 + j * CHUNK, c1);
+    const uint32_t hi = min(lo + CHUNK, c1);
+    if (lo == hi) return;
+    float rx[LVL_P][D];
+    uint32_t rid[LVL_P], w[LVL_P];
+    // thread t holds records lo + t + 1024 k: the valid ones are a prefix in k
+    uint32_t nact = 0;
+#pragma unroll
+    for (int k = 0; k < LVL_P; ++k) {
+        const uint32_t e = lo + threadIdx.x + k * LVL_TPB;
+        Rec<D> t{};
+        w[k] = 0u;
+        if (e < hi) {
+            t = in[e];
+            w[k] = win[e];
+            ++nact;
+        }
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) rx[k][cc] = t.x[cc];
+        rid[k] = t.id;
+    }
+    const uint32_t ndig = 1u << shift;
+    staged_write<D>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
+}
+
 // ---------------------------------------------------------------------------
-// 4. per-bucket sort + batch force + Euler-Maruyama
+// per-bucket sort + batch force + Euler-Maruyama
 // ---------------------------------------------------------------------------
-// SINGLE: the whole system is one bucket read from the slot-ordered state;
-// the PERM words are drawn here.  fout != nullptr: forces only (written by
-// id, state untouched; dst receives only the records the fix-up needs).
-template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SBITS>
+// Write-back of one particle: the force (by id) in force mode, else the
+// Euler-Maruyama update written at sorted rank r.
+template <int D>
+__device__ __forceinline__ void finish(const StepArgs &s, float (&x)[D], float (&f)[D], uint32_t id,
+                                       uint32_t r, Rec<D> *dst, float *__restrict__ fout)
+{
+    if (fout) {
+        if (id < s.n) {  // ids are < N unless a flagged overflow left stale data
+#pragma unroll
+            for (int c = 0; c < D; ++c) fout[(size_t)id * D + c] = f[c];
+        }
+        return;
+    }
+    em_update<D>(s, x, f, id);
+    Rec<D> o;
+#pragma unroll
+    for (int c = 0; c < D; ++c) o.x[c] = x[c];
+    o.id = id;
+    dst[r] = o;
+}
+
+// A batch of exactly P members b[0..P) at ranks bs..bs+P: every unordered
+// pair is evaluated once and applied with both signs (K is odd).
+template <int D, int KERN, int P>
+__device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, uint32_t bs,
+                                           Rec<D> *dst, float *__restrict__ fout)
+{
+    float x[P][D], f[P][D];
+    uint32_t id[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const Rec<D> r = b[i];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            x[i][c] = r.x[c];
+            f[i][c] = 0.0f;
+        }
+        id[i] = r.id;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < P; ++j) {
+            float dx[D], r2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                dx[c] = x[i][c] - x[j][c];
+                r2 = fmaf(dx[c], dx[c], r2);
+            }
+            const float sc = pair_scale<KERN>(r2, s.a);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                f[i][c] = fmaf(sc, dx[c], f[i][c]);
+                f[j][c] = fmaf(-sc, dx[c], f[j][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) f[i][c] *= s.inv_p1;
+        finish<D>(s, x[i], f[i], id[i], bs + i, dst, fout);
+    }
+}
+
+// Member i of a batch b[0..sz) of any size: its force by direct summation.
+template <int D, int KERN>
+__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *b, uint32_t sz,
+                                               uint32_t i, uint32_t bs, Rec<D> *dst,
+                                               float *__restrict__ fout)
+{
+    const Rec<D> me = b[i];
+    float xi[D], f[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        xi[c] = me.x[c];
+        f[c] = 0.0f;
+    }
+    for (uint32_t j = 0; j < sz; ++j)
+        if (j != i) add_pair<D, KERN>(xi, b[j].x, s.a, f);
+    const float inv = (sz == s.p) ? s.inv_p1 : s.inv_last;
+#pragma unroll
+    for (int c = 0; c < D; ++c) f[c] *= inv;
+    finish<D>(s, xi, f, me.id, bs + i, dst, fout);
+}
+
+// One workgroup per fine bucket [lo, hi) (SINGLE: the whole system, read
+// from the slot-ordered state, PERM words drawn here).
+//   1. load: records stay in registers; words and ids go to LDS; each record
+//      is counted in its sub-bucket (the next SBITS bits of the word below
+//      the bucket digits)
+//   2. exclusive scan of the sub-bucket counts; member lists per sub-bucket
+//   3. rank = sub-bucket start + members with a smaller (w, id) key
+//   4. records written to LDS in sorted order (reusing the ordering bytes)
+//   5. batches inside the bucket: P > 0, one thread per batch of P (pairs
+//      once, antisymmetric); P = 0, one thread per record.  Records of cut
+//      batches go to dst unchanged for k_fixup.
+// fout != nullptr: forces only (by id); dst gets only the cut batches.
+template <int D, int KERN, int P, bool SINGLE, int TPB, int CAP, int SBITS>
 __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src,
                                                    const uint32_t *__restrict__ wsrc,
                                                    const uint32_t *__restrict__ bstart,
@@ -211,12 +461,15 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     constexpr int S = 1 << SBITS;
     constexpr int E = (CAP + TPB - 1) / TPB;
     static_assert(S % TPB == 0, "sub-bucket count must be a multiple of the block");
-    __shared__ Rec<D> rec[CAP];
-    __shared__ uint32_t wv[CAP];
-    __shared__ uint32_t cnt[S + 1];
-    __shared__ uint16_t tmp[CAP];
-    __shared__ uint16_t ord[CAP];
+    constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
+    constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
+    __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
     __shared__ uint32_t scan_tmp[TPB / 64];
+    uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
+    uint32_t *idv = wv + CAP;
+    uint32_t *cnt = idv + CAP;
+    uint16_t *tmp = reinterpret_cast<uint16_t *>(cnt + S + 1);
+    Rec<D> *srec = reinterpret_cast<Rec<D> *>(lds);
 
     const uint32_t tid = threadIdx.x;
     uint32_t lo, hi;
@@ -237,13 +490,17 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     for (uint32_t i = tid; i <= (uint32_t)S; i += TPB) cnt[i] = 0;
     __syncthreads();
 
-    // load, draw/fetch the PERM word, count per sub-bucket
-    uint32_t my_sb[E], my_pos[E];
+    // 1. load
+    float mx[E][D];
+    uint32_t mid[E], msb[E], mpos[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
         if (e < nb) {
-            rec[e] = src[lo + e];
+            const Rec<D> r = src[lo + e];
+#pragma unroll
+            for (int c = 0; c < D; ++c) mx[k][c] = r.x[c];
+            mid[k] = r.id;
             uint32_t w;
             if constexpr (SINGLE) {
                 const uint4 b4 = philox4x32_10(make_uint4(e >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
@@ -252,81 +509,96 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
                 w = wsrc[lo + e];
             }
             wv[e] = w;
+            idv[e] = r.id;
             const uint32_t sb = (w * s.nbuck) >> (32 - SBITS);
-            my_sb[k] = sb;
-            my_pos[k] = atomicAdd(&cnt[sb], 1u);
+            msb[k] = sb;
+            mpos[k] = atomicAdd(&cnt[sb], 1u);
         }
     }
     __syncthreads();
+    // 2. sub-bucket starts and member lists
     const uint32_t total = block_exclusive_scan<TPB, S / TPB>(cnt, scan_tmp);
     if (tid == 0) cnt[S] = total;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
-        if (e < nb) tmp[cnt[my_sb[k]] + my_pos[k]] = (uint16_t)e;
+        if (e < nb) tmp[cnt[msb[k]] + mpos[k]] = (uint16_t)e;
     }
     __syncthreads();
-    // exact rank: position of the sub-bucket plus the members with smaller key
+    // 3. exact ranks
+    uint32_t mrank[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
+        mrank[k] = 0;
         if (e < nb) {
             const uint32_t w = wv[e];
-            const uint32_t id = rec[e].id;
-            const uint32_t b0 = cnt[my_sb[k]], b1 = cnt[my_sb[k] + 1];
+            const uint32_t id = mid[k];
+            const uint32_t b0 = cnt[msb[k]], b1 = cnt[msb[k] + 1];
             uint32_t rank = b0;
             for (uint32_t j = b0; j < b1; ++j) {
                 const uint32_t t = tmp[j];
                 const uint32_t wt = wv[t];
-                rank += (wt < w || (wt == w && rec[t].id < id)) ? 1u : 0u;
+                rank += (wt < w || (wt == w && idv[t] < id)) ? 1u : 0u;
             }
-            ord[rank] = (uint16_t)e;
+            mrank[k] = rank;
+        }
+    }
+    __syncthreads();
+    // 4. sorted records
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t e = tid + k * TPB;
+        if (e < nb) {
+            Rec<D> r;
+#pragma unroll
+            for (int c = 0; c < D; ++c) r.x[c] = mx[k][c];
+            r.id = mid[k];
+            srec[mrank[k]] = r;
         }
     }
     __syncthreads();
 
-    // batches inside the bucket: force, update, write at the sorted rank
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        const uint32_t l = tid + k * TPB;
-        if (l < nb) {
-            const uint32_t r = lo + l;
-            const Rec<D> me = rec[ord[l]];
+    // 5. batches.  The batches [bs, be) with lo <= bs and be <= hi are
+    //    q_first..q_last; they cover ranks [ins_lo, ins_hi).  The last batch
+    //    (q = nbat - 1) ends at n, so it is inside only if hi == n.
+    const uint32_t p = s.p;
+    const int64_t q_first = ((int64_t)lo + p - 1) / p;
+    const int64_t q_last = (hi == s.n) ? (int64_t)s.nbat - 1
+                                       : min((int64_t)s.nbat - 2, (int64_t)(hi / p) - 1);
+    const bool any = q_first <= (int64_t)s.nbat - 1 && q_last >= q_first;
+    const uint32_t ins_lo = any ? (uint32_t)q_first * p : hi;
+    const uint32_t ins_hi = any ? (q_last == (int64_t)s.nbat - 1 ? s.n : (uint32_t)(q_last + 1) * p) : hi;
+    for (uint32_t l = tid; l < nb; l += TPB) {
+        const uint32_t r = lo + l;
+        if (r < ins_lo || r >= ins_hi) dst[r] = srec[l];
+    }
+    if (!any) return;
+    if constexpr (P > 0) {
+        const uint32_t nq = (uint32_t)(q_last - q_first + 1);
+        for (uint32_t qq = tid; qq < nq; qq += TPB) {
+            const uint32_t q = (uint32_t)q_first + qq;
+            const uint32_t bs = q * p;
+            const uint32_t sz = (q == s.nbat - 1) ? s.n - bs : p;
+            const Rec<D> *b = srec + (bs - lo);
+            if (sz == (uint32_t)P) {
+                batch_fast<D, KERN, P>(s, b, bs, dst, fout);
+            } else {
+                for (uint32_t i = 0; i < sz; ++i) member_generic<D, KERN>(s, b, sz, i, bs, dst, fout);
+            }
+        }
+    } else {
+        for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
             uint32_t bs, be;
             batch_of(s, r, bs, be);
-            if (bs >= lo && be <= hi) {
-                float xi[D], f[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    xi[c] = me.x[c];
-                    f[c] = 0.0f;
-                }
-                for (uint32_t j = bs; j < be; ++j)
-                    if (j != r) add_pair<D, KERN>(xi, rec[ord[j - lo]].x, s.a, f);
-                const float inv = 1.0f / (float)(be - bs - 1);
-#pragma unroll
-                for (int c = 0; c < D; ++c) f[c] *= inv;
-                if (fout) {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) fout[(size_t)me.id * D + c] = f[c];
-                } else {
-                    em_update<D>(s, xi, f, me.id);
-                    Rec<D> o;
-#pragma unroll
-                    for (int c = 0; c < D; ++c) o.x[c] = xi[c];
-                    o.id = me.id;
-                    dst[r] = o;
-                }
-            } else {
-                dst[r] = me;  // batch cut by a bucket boundary: k_fixup completes it
-            }
+            member_generic<D, KERN>(s, srec + (bs - lo), be - bs, r - bs, bs, dst, fout);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// 5. batches cut by bucket boundaries
+// batches cut by bucket boundaries
 // ---------------------------------------------------------------------------
 // Workgroup b-1 looks at the boundary at rank bstart[b].  The batch around it
 // is cut if the boundary is not the batch's first rank; of several
@@ -357,12 +629,14 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
         }
         for (uint32_t j = 0; j < sz; ++j)
             if (j != tid) add_pair<D, KERN>(xi, sh[j].x, s.a, f);
-        const float inv = 1.0f / (float)(sz - 1);
+        const float inv = (sz == s.p) ? s.inv_p1 : s.inv_last;
 #pragma unroll
         for (int c = 0; c < D; ++c) f[c] *= inv;
         if (fout) {
+            if (me.id < s.n) {
 #pragma unroll
-            for (int c = 0; c < D; ++c) fout[(size_t)me.id * D + c] = f[c];
+                for (int c = 0; c < D; ++c) fout[(size_t)me.id * D + c] = f[c];
+            }
         } else {
             em_update<D>(s, xi, f, me.id);
             Rec<D> o;
@@ -488,65 +762,105 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int SORT_TPB = 512;
+constexpr int SINGLE_TPB = 512;
+constexpr int SINGLE_CAP = RBM_SINGLE_CAP;
+constexpr int SINGLE_SBITS = 11;
+constexpr int SORT_TPB = 256;
 constexpr int SORT_CAP = RBM_SORT_CAP;
-constexpr int SORT_SBITS = 11;
-constexpr int COUNT_TPB = 1024;
-constexpr int SCATTER_TPB = 1024;
+constexpr int SORT_SBITS = 10;
 constexpr int DIRECT_TPB = 256;
-
-hipError_t last()
-{
-    return hipGetLastError();
-}
 
 inline void mark(hipEvent_t *ev, int i, hipStream_t st)
 {
     if (ev) (void)hipEventRecord(ev[i], st);
 }
 
+template <typename T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>((char *)ws + off);
+}
+
+// The sort kernel specialised on the batch size (one thread per batch) for
+// the common sizes; any other p takes the one-thread-per-record form.
+template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB>
+void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const Rec<D> *src,
+                 const uint32_t *wsrc, const uint32_t *bstart, Rec<D> *dst, float *fout,
+                 uint32_t *flags)
+{
+#define RBM_SORT(PP)                                                                              \
+    hipLaunchKernelGGL((k_sort_step<D, KERN, PP, SINGLE, TPB, CAP, SB>), grid, dim3(TPB), 0, st, s, \
+                       src, wsrc, bstart, dst, fout, flags)
+    switch (p) {
+    case 2: RBM_SORT(2); break;
+    case 4: RBM_SORT(4); break;
+    case 8: RBM_SORT(8); break;
+    default: RBM_SORT(0); break;
+    }
+#undef RBM_SORT
+}
+
 template <int D, int KERN>
 hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, void *dst_state,
                    float *fout, hipEvent_t *ev)
 {
-    auto *state = reinterpret_cast<Rec<D> *>((char *)ws + pl.off_state);
+    auto *state = at<Rec<D>>(ws, pl.off_state);
     auto *dst = reinterpret_cast<Rec<D> *>(dst_state);
-    auto *flags = reinterpret_cast<uint32_t *>((char *)ws + pl.off_flags);
+    auto *flags = at<uint32_t>(ws, pl.off_flags);
     if (pl.nbuck == 1) {
-        for (int i = 0; i <= 4; ++i) mark(ev, i, st);
-        hipLaunchKernelGGL((k_sort_step<D, KERN, true, SORT_TPB, SORT_CAP, SORT_SBITS>), dim3(1),
-                           dim3(SORT_TPB), 0, st, s, state, nullptr, nullptr, dst, fout, flags);
-        mark(ev, 5, st);
+        for (int i = 0; i <= 5; ++i) mark(ev, i, st);
+        launch_sort<D, KERN, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS>(
+            pl.p, dim3(1), st, s, state, nullptr, nullptr, dst, fout, flags);
         mark(ev, 6, st);
-        return last();
+        mark(ev, 7, st);
+        return hipGetLastError();
     }
-    auto *stage = reinterpret_cast<Rec<D> *>((char *)ws + pl.off_stage);
-    auto *wbuf = reinterpret_cast<uint32_t *>((char *)ws + pl.off_w);
-    auto *cnt = reinterpret_cast<uint32_t *>((char *)ws + pl.off_cnt);
-    auto *tot = reinterpret_cast<uint32_t *>((char *)ws + pl.off_tot);
-    auto *bstart = reinterpret_cast<uint32_t *>((char *)ws + pl.off_bstart);
-    const size_t lds = (size_t)pl.nbuck * sizeof(uint32_t);
+    auto *stage1 = at<Rec<D>>(ws, pl.off_stage1);
+    auto *w1 = at<uint32_t>(ws, pl.off_w1);
+    auto *kcnt = at<uint32_t>(ws, pl.off_kcnt);
+    auto *ftot = at<uint32_t>(ws, pl.off_ftot);
+    auto *fstart = at<uint32_t>(ws, pl.off_fstart);
+    auto *fcur = at<uint32_t>(ws, pl.off_fcur);
+    auto *cstart = at<uint32_t>(ws, pl.off_cstart);
+    auto *ccur = at<uint32_t>(ws, pl.off_ccur);
+    const bool split = pl.shift > 0;
     mark(ev, 0, st);
-    hipLaunchKernelGGL((k_bucket_count<COUNT_TPB>), dim3(pl.ntiles), dim3(COUNT_TPB), lds, st, s,
-                       pl.tile, cnt);
+    hipLaunchKernelGGL(k_key_count, dim3(pl.ntf), dim3(1024), (size_t)pl.nbuck * 4, st, s, pl.tilef,
+                       kcnt);
     mark(ev, 1, st);
-    hipLaunchKernelGGL(k_bucket_colscan, dim3((pl.nbuck + 255) / 256), dim3(256), 0, st,
-                       pl.ntiles, pl.nbuck, cnt, tot);
+    hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256), dim3(256), 0, st, pl.ntf,
+                       pl.nbuck, kcnt, ftot);
     mark(ev, 2, st);
-    hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, (uint32_t)SORT_CAP,
-                       tot, bstart, flags);
+    hipLaunchKernelGGL(k_key_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
+                       (uint32_t)SORT_CAP, split ? pl.jmax * CHUNK : (uint32_t)SORT_CAP, ftot,
+                       fstart, fcur, cstart, ccur, flags);
     mark(ev, 3, st);
-    hipLaunchKernelGGL((k_bucket_scatter<D, SCATTER_TPB>), dim3(pl.ntiles), dim3(SCATTER_TPB), lds,
-                       st, s, pl.tile, state, stage, wbuf, cnt, bstart);
-    mark(ev, 4, st);
-    hipLaunchKernelGGL((k_sort_step<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>),
-                       dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, stage, wbuf, bstart, dst, fout,
-                       flags);
-    mark(ev, 5, st);
-    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, bstart, dst,
-                       fout);
+    const Rec<D> *src = stage1;
+    const uint32_t *wsrc = w1;
+    if (split) {
+        auto *stage2 = at<Rec<D>>(ws, pl.off_stage2);
+        auto *w2 = at<uint32_t>(ws, pl.off_w2);
+        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, pl.shift,
+                           pl.nb1, state, ccur, stage1, w1);
+        mark(ev, 4, st);
+        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(LVL_TPB), 0, st, s, pl.shift,
+                           pl.jmax, cstart, stage1, w1, fcur, stage2, w2);
+        mark(ev, 5, st);
+        src = stage2;
+        wsrc = w2;
+    } else {
+        // one level: the coarse buckets are the fine buckets
+        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, 0u,
+                           pl.nbuck, state, fcur, stage1, w1);
+        mark(ev, 4, st);
+        mark(ev, 5, st);
+    }
+    launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
+                                                                fstart, dst, fout, flags);
     mark(ev, 6, st);
-    return last();
+    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, fout);
+    mark(ev, 7, st);
+    return hipGetLastError();
 }
 
 template <int D>
@@ -566,7 +880,7 @@ hipError_t direct_dk(const StepArgs &s, const float *x, const uint32_t *ids, uin
 {
     hipLaunchKernelGGL((k_direct<D, KERN, DIRECT_TPB>), dim3((nids + DIRECT_TPB - 1) / DIRECT_TPB),
                        dim3(DIRECT_TPB), 0, st, s, x, ids, nids, out, step);
-    return last();
+    return hipGetLastError();
 }
 
 template <int D>
@@ -595,8 +909,8 @@ hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, voi
 hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *slots, void *ws,
                        hipStream_t st)
 {
-    void *state = (char *)ws + pl.off_state;
-    auto *flags = reinterpret_cast<uint32_t *>((char *)ws + pl.off_flags);
+    void *state = at<char>(ws, pl.off_state);
+    auto *flags = at<uint32_t>(ws, pl.off_flags);
     const dim3 g((pl.n + 255) / 256);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, flags, 16u, 0u);
     switch (d) {
@@ -604,7 +918,7 @@ hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *s
     case 2: hipLaunchKernelGGL(k_init_state<2>, g, dim3(256), 0, st, pl.n, x0, slots, (Rec<2> *)state, flags); break;
     default: hipLaunchKernelGGL(k_init_state<3>, g, dim3(256), 0, st, pl.n, x0, slots, (Rec<3> *)state, flags); break;
     }
-    return last();
+    return hipGetLastError();
 }
 
 hipError_t launch_positions(const Plan &pl, int d, const void *ws, float *x, uint32_t *ids,
@@ -617,7 +931,7 @@ hipError_t launch_positions(const Plan &pl, int d, const void *ws, float *x, uin
     case 2: hipLaunchKernelGGL(k_positions<2>, g, dim3(256), 0, st, pl.n, (const Rec<2> *)state, x, ids); break;
     default: hipLaunchKernelGGL(k_positions<3>, g, dim3(256), 0, st, pl.n, (const Rec<3> *)state, x, ids); break;
     }
-    return last();
+    return hipGetLastError();
 }
 
 hipError_t launch_direct(const StepArgs &s, int d, int kernel, const float *x, const uint32_t *ids,

@@ -8,28 +8,40 @@
 
 #include "rbm_device.hpp"
 
-// Records one sort workgroup holds in LDS (75 KB at d = 3, so two
-// workgroups share a CU's 160 KB).  Buckets average RBM_BUCKET_MEAN records;
-// a bucket above the capacity is 17 standard deviations out.
-#define RBM_SORT_CAP 2816
-#define RBM_BUCKET_MEAN 2048
-#define RBM_MAX_BUCKETS 16384
+// Capacity of the one-workgroup path (the whole system in LDS, 75 KB at
+// d = 3).
+#define RBM_SINGLE_CAP 2816
+// Fine buckets average RBM_BUCKET_MEAN records; a sort workgroup holds up to
+// RBM_SORT_CAP (15 standard deviations above the mean) in 40 KB of LDS, so
+// four workgroups share a CU.
+#define RBM_BUCKET_MEAN 1024
+#define RBM_SORT_CAP 1520
+#define RBM_MAX_FINE 32768
+#define RBM_TILE 16384
+#define RBM_CHUNK 16384
+#define RBM_SPLIT_SHIFT 7
 
 namespace rbm {
+
+// Kernel phases of one step (the order of include/rbm.h's RBM_PHASE_*).
+constexpr int RBM_NPH = 7;
 
 struct Plan {
     uint32_t n, p, nbat;
     int d, kernel;
-    uint32_t nbuck;   // 1: the whole system is sorted by one workgroup
-    uint32_t tile;    // slots per count/scatter workgroup (multiple of 4)
-    uint32_t ntiles;
+    uint32_t nbuck;   // fine buckets (1: the whole system is sorted by one workgroup)
+    uint32_t nb1;     // coarse buckets
+    uint32_t shift;   // log2(fine buckets per coarse bucket), 0 without a split level
+    uint32_t jmax;    // split chunks per coarse bucket
+    uint32_t ntiles;  // coarse-scatter tiles of RBM_TILE slots
+    uint32_t tilef;   // slots per key-count tile
+    uint32_t ntf;     // key-count tiles
     size_t rec_bytes;
-    size_t off_state, off_stage, off_w, off_scratch, off_cnt, off_tot, off_bstart, off_flags;
+    size_t off_state, off_scratch, off_stage1, off_w1, off_stage2, off_w2;
+    size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;
     size_t total;
 };
 
-// ev: NULL, or RBM_NPHASES + 1 events recorded before the first and after
-// every phase of the step.
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev);
 hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *slots, void *ws,
