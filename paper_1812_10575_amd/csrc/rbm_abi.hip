@@ -22,6 +22,7 @@ struct rbm_ctx {
     Plan plan;
     void *ws;
     int64_t m;  // index of the next step
+    bool pending;  // stored positions lack the noise of step m - 1
     // per-phase timing (measurement aid)
     hipEvent_t *ev;   // tmax * (RBM_NPHASES + 1) events
     int32_t tmax;     // steps the pool can record
@@ -140,7 +141,8 @@ Plan make_plan(const rbm_params *prm)
     return pl;
 }
 
-StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m)
+// pending: the stored positions lack the noise of step m - 1.
+StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m, bool pending)
 {
     StepArgs s{};
     s.n = pl.n;
@@ -157,6 +159,8 @@ StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m)
     s.beta = (float)prm->beta;
     s.dt = (float)prm->dt;
     s.ssd = (float)(prm->sigma * std::sqrt(prm->dt));
+    s.pm = m - 1u;
+    s.pssd = pending ? s.ssd : 0.0f;
     return s;
 }
 
@@ -237,13 +241,14 @@ rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
     const Plan &pl = ctx->plan;
     void *state = (char *)ctx->ws + pl.off_state;
     for (int64_t k = 0; k < nsteps; ++k) {
-        const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)ctx->m);
+        const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)ctx->m, ctx->pending);
         hipEvent_t *ev = nullptr;
         if (ctx->trec < ctx->tmax) ev = ctx->ev + (size_t)ctx->trec++ * (RBM_NPHASES + 1);
         hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, (hipStream_t)stream, state,
                                         nullptr, ev);
         if (e != hipSuccess) return hip_fail(e, "rbm_step launch");
         ctx->m += 1;
+        ctx->pending = s.ssd != 0.0f;
     }
     return RBM_OK;
 }
@@ -253,7 +258,8 @@ rbm_status rbm_positions(rbm_ctx *ctx, float *d_x, void *stream)
     rbm_status st = check_ctx(ctx);
     if (st != RBM_OK) return st;
     if (!d_x) return fail(RBM_ERR_INVALID, "d_x is NULL");
-    hipError_t e = rbm::launch_positions(ctx->plan, ctx->plan.d, ctx->ws, d_x, nullptr,
+    const StepArgs s = make_args(&ctx->prm, ctx->plan, (uint32_t)ctx->m, ctx->pending);
+    hipError_t e = rbm::launch_positions(ctx->plan, s, ctx->plan.d, ctx->ws, d_x, nullptr,
                                          (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "rbm_positions launch");
 }
@@ -263,7 +269,8 @@ rbm_status rbm_perm(rbm_ctx *ctx, uint32_t *d_ids, void *stream)
     rbm_status st = check_ctx(ctx);
     if (st != RBM_OK) return st;
     if (!d_ids) return fail(RBM_ERR_INVALID, "d_ids is NULL");
-    hipError_t e = rbm::launch_positions(ctx->plan, ctx->plan.d, ctx->ws, nullptr, d_ids,
+    const StepArgs s = make_args(&ctx->prm, ctx->plan, (uint32_t)ctx->m, ctx->pending);
+    hipError_t e = rbm::launch_positions(ctx->plan, s, ctx->plan.d, ctx->ws, nullptr, d_ids,
                                          (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "rbm_perm launch");
 }
@@ -275,7 +282,9 @@ rbm_status rbm_forces(rbm_ctx *ctx, int64_t step, float *d_f, void *stream)
     if (!d_f) return fail(RBM_ERR_INVALID, "d_f is NULL");
     if (step < 0 || step > 0xffffffffLL) return fail(RBM_ERR_INVALID, "step out of range");
     const Plan &pl = ctx->plan;
-    const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)step);
+    StepArgs s = make_args(&ctx->prm, pl, (uint32_t)step, false);
+    s.pm = (uint32_t)(ctx->m - 1);
+    s.pssd = ctx->pending ? s.ssd : 0.0f;
     void *scratch = (char *)ctx->ws + pl.off_scratch;
     hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, (hipStream_t)stream, scratch, d_f,
                                     nullptr);
@@ -385,7 +394,7 @@ rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t
     if (nids < 0 || nids > prm->n) return fail(RBM_ERR_INVALID, "nids out of range");
     if (nids == 0) return RBM_OK;
     const Plan pl = make_plan(prm);
-    const StepArgs s = make_args(prm, pl, 0);
+    const StepArgs s = make_args(prm, pl, 0, false);
     hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, d_ids, (uint32_t)nids, d_f, 0,
                                       (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_forces launch");
@@ -401,7 +410,7 @@ rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out, 
     if (d_x == d_x_out) return fail(RBM_ERR_INVALID, "d_x_out must not alias d_x");
     if (step < 0 || step > 0xffffffffLL) return fail(RBM_ERR_INVALID, "step out of range");
     const Plan pl = make_plan(prm);
-    const StepArgs s = make_args(prm, pl, (uint32_t)step);
+    const StepArgs s = make_args(prm, pl, (uint32_t)step, false);
     hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, nullptr, (uint32_t)prm->n,
                                       d_x_out, 1, (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_step launch");

@@ -135,6 +135,8 @@ struct StepArgs {
     float beta;      // -grad V = -beta x
     float dt;        // time step
     float ssd;       // sigma * sqrt(dt)
+    uint32_t pm;     // step whose noise the stored positions still lack
+    float pssd;      // its amplitude (0: none pending)
 };
 
 // Batch [bs, be) of sorted rank r: groups of p, the last also takes the
@@ -147,7 +149,29 @@ __device__ __forceinline__ void batch_of(const StepArgs &s, uint32_t r, uint32_t
     be = (q == s.nbat - 1) ? s.n : bs + s.p;
 }
 
-// Forward Euler-Maruyama: x <- x + dt (-beta x + F) + sigma sqrt(dt) z.
+// The drift part of the step, x <- x + dt (-beta x + F).  The noise of the
+// same step, sigma sqrt(dt) z(id, m), is added by whichever kernel reads the
+// positions next (deferred noise, below), where the ALU is otherwise idle.
+template <int D>
+__device__ __forceinline__ void drift_update(const StepArgs &s, float (&x)[D], const float (&f)[D])
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = x[k] + s.dt * (-s.beta * x[k] + f[k]);
+}
+
+// Add the noise the stored positions still lack: sigma sqrt(dt) z(id, pm).
+template <int D>
+__device__ __forceinline__ void add_pending_noise(const StepArgs &s, float *x, uint32_t id)
+{
+    if (s.pssd != 0.0f) {
+        float z[D];
+        noise<D>(id, s.pm, s.sys, s.k0, s.k1, z);
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = x[k] + s.pssd * z[k];
+    }
+}
+
+// Forward Euler-Maruyama in one go: x <- x + dt (-beta x + F) + sigma sqrt(dt) z.
 template <int D>
 __device__ __forceinline__ void em_update(const StepArgs &s, float (&x)[D], const float (&f)[D],
                                           uint32_t id)

@@ -119,7 +119,7 @@ __device__ __forceinline__ uint32_t wave0_exclusive_scan(const uint32_t *a, uint
 // ---------------------------------------------------------------------------
 constexpr uint32_t TILE = RBM_TILE;    // slots per coarse-scatter workgroup
 constexpr uint32_t CHUNK = RBM_CHUNK;  // records per split workgroup
-constexpr int LVL_TPB = 1024;          // 16 records per thread
+constexpr int LVL_TPB = RBM_LVL_TPB;   // 16 records per thread
 constexpr int LVL_P = 16;
 constexpr int LVL_NB = 256;            // largest digit count of a level
 
@@ -151,16 +151,26 @@ __global__ __launch_bounds__(256) void k_key_colsum(uint32_t ntf, uint32_t nbuck
     const uint32_t f = blockIdx.x * 256 + threadIdx.x;
     if (f >= nbuck) return;
     uint32_t sum = 0;
-    for (uint32_t t = 0; t < ntf; ++t) sum += cnt[(size_t)t * nbuck + f];
+    uint32_t t = 0;
+    for (; t + 8 <= ntf; t += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cnt[(size_t)(t + u) * nbuck + f];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; t < ntf; ++t) sum += cnt[(size_t)t * nbuck + f];
     ftot[f] = sum;
 }
 
 // One workgroup: fine starts (fstart[nbuck] = N), coarse starts
 // cstart[c] = fstart[c << shift], and the run cursors of both levels.
-// flags bit 0: a fine bucket above the sort capacity or a coarse bucket
-// above ccap records.
+// Global memory is read and written in coalesced order through LDS; thread t
+// scans the PER consecutive totals it owns (the LDS index is padded by one
+// word per 32 so these strided reads hit distinct banks).  flags bit 0: a
+// fine bucket above the sort capacity.
 __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb1, uint32_t shift,
-                                                     uint32_t n, uint32_t fcap, uint32_t ccap,
+                                                     uint32_t n, uint32_t fcap,
                                                      const uint32_t *__restrict__ ftot,
                                                      uint32_t *__restrict__ fstart,
                                                      uint32_t *__restrict__ fcur,
@@ -169,28 +179,46 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
                                                      uint32_t *__restrict__ flags)
 {
     constexpr int TPB = 1024, PER = RBM_MAX_FINE / TPB;
-    __shared__ uint32_t a[TPB * PER];
+    static_assert(PER == 32, "padding assumes 32 entries per thread");
+    __shared__ uint32_t a[RBM_MAX_FINE + RBM_MAX_FINE / 32];
+    __shared__ uint32_t part[TPB];
     __shared__ uint32_t tmp[TPB / 64];
+    auto pad = [](uint32_t i) { return i + (i >> 5); };
+    const uint32_t t = threadIdx.x;
     bool over = false;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(TPB * PER); i += TPB) {
+    for (uint32_t i = t; i < (uint32_t)RBM_MAX_FINE; i += TPB) {
         const uint32_t v = i < nbuck ? ftot[i] : 0u;
-        a[i] = v;
+        a[pad(i)] = v;
         over |= v > fcap;
     }
     __syncthreads();
-    block_exclusive_scan<TPB, PER>(a, tmp);
-    for (uint32_t i = threadIdx.x; i < nbuck; i += TPB) {
-        fstart[i] = a[i];
-        fcur[i] = a[i];
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = a[pad(t * PER + k)];
+        sum += v[k];
     }
-    for (uint32_t c = threadIdx.x; c < nb1; c += TPB) {
-        const uint32_t c0 = a[c << shift];
-        const uint32_t c1 = c + 1 < nb1 ? a[(c + 1) << shift] : n;
-        cstart[c] = c0;
-        ccur[c] = c0;
-        over |= c1 - c0 > ccap;
+    part[t] = sum;
+    __syncthreads();
+    block_exclusive_scan<TPB, 1>(part, tmp);
+    uint32_t run = part[t];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        a[pad(t * PER + k)] = run;
+        run += v[k];
     }
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    for (uint32_t i = t; i < nbuck; i += TPB) {
+        const uint32_t x = a[pad(i)];
+        fstart[i] = x;
+        fcur[i] = x;
+    }
+    for (uint32_t c = t; c < nb1; c += TPB) {
+        const uint32_t x = a[pad(c << shift)];
+        cstart[c] = x;
+        ccur[c] = x;
+    }
+    if (t == 0) {
         fstart[nbuck] = n;
         cstart[nb1] = n;
     }
@@ -298,7 +326,10 @@ __global__ __launch_bounds__(LVL_TPB) void k_scatter_coarse(StepArgs s, uint32_t
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             Rec<D> t{};
-            if (k + j < end) t = state[k + j];
+            if (k + j < end) {
+                t = state[k + j];
+                add_pending_noise<D>(s, t.x, t.id);
+            }
 #pragma unroll
             for (int c = 0; c < D; ++c) rx[4 * g + j][c] = t.x[c];
             rid[4 * g + j] = t.id;
@@ -320,11 +351,14 @@ __global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, u
                                                    const uint32_t *__restrict__ win,
                                                    uint32_t *__restrict__ fcur,
                                                    Rec<D> *__restrict__ out,
-                                                   uint32_t *__restrict__ wout)
+                                                   uint32_t *__restrict__ wout,
+                                                   uint32_t *__restrict__ flags)
 {
     __shared__ StageLds<D> L;
     const uint32_t c = blockIdx.x / jmax, j = blockIdx.x % jmax;
     const uint32_t c0 = cstart[c], c1 = cstart[c + 1];
+    // the jmax chunks must cover the coarse bucket (mean + 16 sd of room)
+    if (j == 0 && threadIdx.x == 0 && c1 - c0 > jmax * CHUNK) atomicOr(flags, 1u);
     const uint32_t lo = min(c0 + j * CHUNK, c1);
     const uint32_t hi = min(lo + CHUNK, c1);
     if (lo == hi) return;
@@ -366,7 +400,7 @@ __device__ __forceinline__ void finish(const StepArgs &s, float (&x)[D], float (
         }
         return;
     }
-    em_update<D>(s, x, f, id);
+    drift_update<D>(s, x, f);
     Rec<D> o;
 #pragma unroll
     for (int c = 0; c < D; ++c) o.x[c] = x[c];
@@ -418,25 +452,42 @@ __device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, u
     }
 }
 
-// Member i of a batch b[0..sz) of any size: its force by direct summation.
-template <int D, int KERN>
-__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *b, uint32_t sz,
-                                               uint32_t i, uint32_t bs, Rec<D> *dst,
+// LDS slot of the record at global rank r in a bucket starting at lo: one
+// empty slot follows every P ranks (P > 0), so that threads reading whole
+// batches of P records see a lane stride of 4(P + 1) words, which spreads
+// them over all banks.
+template <int P>
+struct Pad {
+    uint32_t lo;
+    __device__ __forceinline__ uint32_t operator()(uint32_t r) const
+    {
+        if constexpr (P > 0)
+            return (r - lo) + r / P - lo / P;
+        else
+            return r - lo;
+    }
+};
+
+// Member r of the batch of ranks [bs, bs + sz) (any size): its force by
+// direct summation.
+template <int D, int KERN, int P>
+__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *srec, Pad<P> pad,
+                                               uint32_t bs, uint32_t sz, uint32_t r, Rec<D> *dst,
                                                float *__restrict__ fout)
 {
-    const Rec<D> me = b[i];
+    const Rec<D> me = srec[pad(r)];
     float xi[D], f[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         xi[c] = me.x[c];
         f[c] = 0.0f;
     }
-    for (uint32_t j = 0; j < sz; ++j)
-        if (j != i) add_pair<D, KERN>(xi, b[j].x, s.a, f);
+    for (uint32_t j = bs; j < bs + sz; ++j)
+        if (j != r) add_pair<D, KERN>(xi, srec[pad(j)].x, s.a, f);
     const float inv = (sz == s.p) ? s.inv_p1 : s.inv_last;
 #pragma unroll
     for (int c = 0; c < D; ++c) f[c] *= inv;
-    finish<D>(s, xi, f, me.id, bs + i, dst, fout);
+    finish<D>(s, xi, f, me.id, r, dst, fout);
 }
 
 // One workgroup per fine bucket [lo, hi) (SINGLE: the whole system, read
@@ -462,7 +513,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     constexpr int E = (CAP + TPB - 1) / TPB;
     static_assert(S % TPB == 0, "sub-bucket count must be a multiple of the block");
     constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
-    constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
+    constexpr size_t REC_BYTES = (size_t)(CAP + (P > 0 ? CAP / P + 2 : 0)) * sizeof(Rec<D>);
     __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
     __shared__ uint32_t scan_tmp[TPB / 64];
     uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
@@ -497,7 +548,8 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
         if (e < nb) {
-            const Rec<D> r = src[lo + e];
+            Rec<D> r = src[lo + e];
+            if constexpr (SINGLE) add_pending_noise<D>(s, r.x, r.id);
 #pragma unroll
             for (int c = 0; c < D; ++c) mx[k][c] = r.x[c];
             mid[k] = r.id;
@@ -547,6 +599,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     }
     __syncthreads();
     // 4. sorted records
+    const Pad<P> pad{lo};
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
@@ -555,7 +608,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
 #pragma unroll
             for (int c = 0; c < D; ++c) r.x[c] = mx[k][c];
             r.id = mid[k];
-            srec[mrank[k]] = r;
+            srec[pad(lo + mrank[k])] = r;
         }
     }
     __syncthreads();
@@ -572,7 +625,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     const uint32_t ins_hi = any ? (q_last == (int64_t)s.nbat - 1 ? s.n : (uint32_t)(q_last + 1) * p) : hi;
     for (uint32_t l = tid; l < nb; l += TPB) {
         const uint32_t r = lo + l;
-        if (r < ins_lo || r >= ins_hi) dst[r] = srec[l];
+        if (r < ins_lo || r >= ins_hi) dst[r] = srec[pad(r)];
     }
     if (!any) return;
     if constexpr (P > 0) {
@@ -581,18 +634,18 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
             const uint32_t q = (uint32_t)q_first + qq;
             const uint32_t bs = q * p;
             const uint32_t sz = (q == s.nbat - 1) ? s.n - bs : p;
-            const Rec<D> *b = srec + (bs - lo);
             if (sz == (uint32_t)P) {
-                batch_fast<D, KERN, P>(s, b, bs, dst, fout);
+                batch_fast<D, KERN, P>(s, srec + pad(bs), bs, dst, fout);
             } else {
-                for (uint32_t i = 0; i < sz; ++i) member_generic<D, KERN>(s, b, sz, i, bs, dst, fout);
+                for (uint32_t i = 0; i < sz; ++i)
+                    member_generic<D, KERN, P>(s, srec, pad, bs, sz, bs + i, dst, fout);
             }
         }
     } else {
         for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
             uint32_t bs, be;
             batch_of(s, r, bs, be);
-            member_generic<D, KERN>(s, srec + (bs - lo), be - bs, r - bs, bs, dst, fout);
+            member_generic<D, KERN, P>(s, srec, pad, bs, be - bs, r, dst, fout);
         }
     }
 }
@@ -638,7 +691,7 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
                 for (int c = 0; c < D; ++c) fout[(size_t)me.id * D + c] = f[c];
             }
         } else {
-            em_update<D>(s, xi, f, me.id);
+            drift_update<D>(s, xi, f);
             Rec<D> o;
 #pragma unroll
             for (int c = 0; c < D; ++c) o.x[c] = xi[c];
@@ -674,12 +727,13 @@ __global__ __launch_bounds__(256) void k_init_state(uint32_t n, const float *__r
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_positions(uint32_t n, const Rec<D> *__restrict__ state,
+__global__ __launch_bounds__(256) void k_positions(StepArgs s, const Rec<D> *__restrict__ state,
                                                    float *__restrict__ x, uint32_t *__restrict__ ids)
 {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    const Rec<D> r = state[k];
+    if (k >= s.n) return;
+    Rec<D> r = state[k];
+    if (x) add_pending_noise<D>(s, r.x, r.id);
     if (x) {
 #pragma unroll
         for (int c = 0; c < D; ++c) x[(size_t)r.id * D + c] = r.x[c];
@@ -832,8 +886,7 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
                        pl.nbuck, kcnt, ftot);
     mark(ev, 2, st);
     hipLaunchKernelGGL(k_key_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
-                       (uint32_t)SORT_CAP, split ? pl.jmax * CHUNK : (uint32_t)SORT_CAP, ftot,
-                       fstart, fcur, cstart, ccur, flags);
+                       (uint32_t)SORT_CAP, ftot, fstart, fcur, cstart, ccur, flags);
     mark(ev, 3, st);
     const Rec<D> *src = stage1;
     const uint32_t *wsrc = w1;
@@ -844,7 +897,7 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
                            pl.nb1, state, ccur, stage1, w1);
         mark(ev, 4, st);
         hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(LVL_TPB), 0, st, s, pl.shift,
-                           pl.jmax, cstart, stage1, w1, fcur, stage2, w2);
+                           pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
         mark(ev, 5, st);
         src = stage2;
         wsrc = w2;
@@ -921,15 +974,15 @@ hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *s
     return hipGetLastError();
 }
 
-hipError_t launch_positions(const Plan &pl, int d, const void *ws, float *x, uint32_t *ids,
-                            hipStream_t st)
+hipError_t launch_positions(const Plan &pl, const StepArgs &s, int d, const void *ws, float *x,
+                            uint32_t *ids, hipStream_t st)
 {
     const void *state = (const char *)ws + pl.off_state;
     const dim3 g((pl.n + 255) / 256);
     switch (d) {
-    case 1: hipLaunchKernelGGL(k_positions<1>, g, dim3(256), 0, st, pl.n, (const Rec<1> *)state, x, ids); break;
-    case 2: hipLaunchKernelGGL(k_positions<2>, g, dim3(256), 0, st, pl.n, (const Rec<2> *)state, x, ids); break;
-    default: hipLaunchKernelGGL(k_positions<3>, g, dim3(256), 0, st, pl.n, (const Rec<3> *)state, x, ids); break;
+    case 1: hipLaunchKernelGGL(k_positions<1>, g, dim3(256), 0, st, s, (const Rec<1> *)state, x, ids); break;
+    case 2: hipLaunchKernelGGL(k_positions<2>, g, dim3(256), 0, st, s, (const Rec<2> *)state, x, ids); break;
+    default: hipLaunchKernelGGL(k_positions<3>, g, dim3(256), 0, st, s, (const Rec<3> *)state, x, ids); break;
     }
     return hipGetLastError();
 }

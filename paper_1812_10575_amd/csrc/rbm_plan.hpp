@@ -17,8 +17,9 @@
 #define RBM_BUCKET_MEAN 1024
 #define RBM_SORT_CAP 1520
 #define RBM_MAX_FINE 32768
-#define RBM_TILE 16384
-#define RBM_CHUNK 16384
+#define RBM_LVL_TPB 512
+#define RBM_TILE (16 * RBM_LVL_TPB)
+#define RBM_CHUNK (16 * RBM_LVL_TPB)
 #define RBM_SPLIT_SHIFT 7
 
 namespace rbm {
@@ -46,8 +47,9 @@ hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, voi
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev);
 hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *slots, void *ws,
                        hipStream_t st);
-hipError_t launch_positions(const Plan &pl, int d, const void *ws, float *x, uint32_t *ids,
-                            hipStream_t st);
+// x != NULL: positions by id, with the pending noise of s added.
+hipError_t launch_positions(const Plan &pl, const StepArgs &s, int d, const void *ws, float *x,
+                            uint32_t *ids, hipStream_t st);
 hipError_t launch_direct(const StepArgs &s, int d, int kernel, const float *x,
                          const uint32_t *ids, uint32_t nids, float *out, int step,
                          hipStream_t st);
