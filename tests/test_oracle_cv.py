@@ -1,0 +1,151 @@
+"""Pins of the control-variate oracle (oracle/cv.py)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import rbm_inputs
+from oracle import cv
+from test_oracle_pins import divisions
+
+
+def rand_theta(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    th = cv.glorot_init(seed % 2, seed=seed) * scale
+    p = cv.unpack(th)
+    for b in ("b1", "b2", "b3"):
+        p[b][...] = 0.3 * rng.standard_normal(p[b].shape)
+    return th
+
+
+@pytest.fixture(scope="module")
+def thetas():
+    return rand_theta(3), rand_theta(4)
+
+
+def test_gelu_closed_forms():
+    assert cv.gelu(np.array(0.0)) == 0.0
+    assert cv.gelu_grad(np.array(0.0)) == pytest.approx(0.5, abs=1e-15)
+    assert cv.gelu(np.array(8.0)) == pytest.approx(8.0, rel=1e-12)
+    assert cv.gelu(np.array(-8.0)) == pytest.approx(0.0, abs=1e-12)
+    z = np.linspace(-4, 4, 41)
+    h = 1e-6
+    np.testing.assert_allclose(cv.gelu_grad(z), (cv.gelu(z + h) - cv.gelu(z - h)) / (2 * h), rtol=1e-7, atol=1e-9)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5, 3.14159, 1e-20, 6.5e4, -7.77e-3], np.float64)
+    rng = np.random.default_rng(0)
+    vals = np.concatenate([vals, rng.standard_normal(5000) * 10.0 ** rng.integers(-6, 6, 5000)])
+    want = torch.tensor(vals, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(cv.bf16(vals), want)
+    assert cv.bf16(np.array([1 + 2 ** -8]))[0] == 1.0               # tie to even
+    assert cv.bf16(np.array([1 + 3 * 2 ** -8]))[0] == 1 + 2 ** -6   # tie to even
+
+
+def test_gradients_match_finite_differences(thetas):
+    ta, tc = thetas
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, 2))
+    y = rng.standard_normal((5, 2))
+    _, ga, gc = cv.loss_and_grads(ta, tc, x, y)
+    h = 1e-6
+    for theta, g, which in ((ta, ga, 0), (tc, gc, 1)):
+        for q in rng.choice(cv.NPARAM, 80, replace=False):
+            tp, tm = theta.copy(), theta.copy()
+            tp[q] += h
+            tm[q] -= h
+            if which == 0:
+                lp = cv.loss_and_grads(tp, tc, x, y)[0]
+                lm = cv.loss_and_grads(tm, tc, x, y)[0]
+            else:
+                lp = cv.loss_and_grads(ta, tp, x, y)[0]
+                lm = cv.loss_and_grads(ta, tm, x, y)[0]
+            fd = (lp - lm) / (2 * h)
+            assert g[q] == pytest.approx(fd, rel=1e-6, abs=1e-9), (which, q)
+
+
+def test_loss_is_half_mean_squared_residual(thetas):
+    ta, tc = thetas
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal((7, 2)), rng.standard_normal((7, 2))
+    a = cv.features(ta, x)
+    c = cv.features(tc, y)
+    res = cv.pair_kernel_gauss(x - y) - np.sum(a * c, axis=2)
+    assert cv.loss_and_grads(ta, tc, x, y)[0] == pytest.approx(0.5 * np.mean(np.sum(res ** 2, axis=1)), rel=1e-14)
+
+
+def _direct_gauss(x):
+    n = x.shape[0]
+    f = np.zeros_like(x)
+    for i in range(n):
+        d = x[i][None] - np.delete(x, i, axis=0)
+        f[i] = cv.pair_kernel_gauss(d).sum(axis=0) / (n - 1)
+    return f
+
+
+@pytest.mark.parametrize("n,p", [(6, 2), (7, 3), (8, 4)])
+def test_cv_force_is_unbiased_for_any_weights(thetas, n, p):
+    """Over every division, the mean control-variate force is the direct
+    force (Lemma 3.1 applied to the residual kernel), and for p | N its
+    variance is (1/(p-1) - 1/(N-1)) Lambda_i[K_res]."""
+    ta, tc = thetas
+    x = rbm_inputs.normal(n, 2, seed=n + 40).astype(np.float64)
+    fs = np.array([cv.cv_forces(ta, tc, x, [i for b in dv for i in b], p) for dv in divisions(n, p)])
+    fd = _direct_gauss(x)
+    np.testing.assert_allclose(fs.mean(axis=0), fd, rtol=0, atol=1e-13)
+    if n % p == 0:
+        a = cv.features(ta, x)
+        c = cv.features(tc, x)
+        var = np.mean(np.sum((fs - fd[None]) ** 2, axis=2), axis=0)
+        for i in range(n):
+            js = [j for j in range(n) if j != i]
+            kres = cv.pair_kernel_gauss(x[i][None] - x[js]) - np.einsum("kr,jkr->jk", a[i], c[js])
+            lam = np.sum((kres - kres.mean(axis=0)) ** 2) / (n - 2)
+            assert var[i] == pytest.approx((1 / (p - 1) - 1 / (n - 1)) * lam, rel=1e-10, abs=1e-16)
+
+
+def test_zero_network_is_plain_rbm():
+    import oracle as ora
+    n, p = 40, 2
+    x = rbm_inputs.normal(n, 2, seed=9).astype(np.float64)
+    z = np.zeros(cv.NPARAM)
+    prm = ora.Params(d=2, kernel=ora.K_GAUSS, kparam=0.0, beta=1.0, sigma=0.0, dt=1e-3)
+    perm = ora.permutation(prm, 3, np.arange(n))
+    np.testing.assert_allclose(cv.cv_forces(z, z, x, perm, p), ora.rbm_forces(prm, p, x, perm), rtol=1e-13, atol=1e-15)
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th, m, v = cv.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
+    # m_hat = g, v_hat = g^2: the first step is -lr g / (|g| + eps)
+    np.testing.assert_allclose(th, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_glorot_init_statistics():
+    th = cv.glorot_init(0, seed=1)
+    p = cv.unpack(th)
+    for name, (fo, fi) in (("W1", (64, 2)), ("W2", (64, 64)), ("W3", (32, 64))):
+        lim = math.sqrt(6 / (fo + fi))
+        w = p[name].ravel()
+        assert np.max(np.abs(w)) <= lim
+        assert abs(w.mean()) < 4 * lim / math.sqrt(3 * w.size)
+        if w.size > 1000:
+            assert w.var() == pytest.approx(lim * lim / 3, rel=0.1)
+    assert np.all(p["b1"] == 0) and np.all(p["b2"] == 0) and np.all(p["b3"] == 0)
+    assert not np.array_equal(cv.glorot_init(0, 1), cv.glorot_init(1, 1))
+
+
+def test_pair_sampler():
+    pr = cv.sample_pairs(0, 4000, 3, 50)
+    assert np.all(pr[:, 1] != pr[:, 2])
+    assert pr[:, 0].min() >= 0 and pr[:, 0].max() <= 2
+    assert pr[:, 1].min() >= 0 and pr[:, 1].max() <= 49 and pr[:, 2].max() <= 49
+    from scipy import stats
+    assert stats.chisquare(np.bincount(pr[:, 1], minlength=50)).pvalue > 1e-4
+    assert stats.chisquare(np.bincount(pr[:, 2], minlength=50)).pvalue > 1e-4
+    assert not np.array_equal(pr, cv.sample_pairs(1, 4000, 3, 50))
