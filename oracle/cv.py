@@ -24,9 +24,10 @@ Network: 2 -> 64 -> 64 -> 32, GELU(z) = z Phi(z) after the two hidden
 layers, linear output.  Parameter vector of one net, in this order:
 W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32] (6432 values).
 
-`bf16=True` rounds (to nearest even) exactly the operands the GPU feeds to
-its BF16 matrix instructions: W2, W3, the hidden activations h1, h2 in the
-forward pass, and dO, delta2 (and the weights) in the backward pass.
+`use_bf16=True` rounds (to nearest even) exactly the operands the GPU feeds
+to its BF16 matrix instructions: W2, W3 and the hidden activations h1, h2 in
+the forward pass; dO, delta2, h1, h2 and the weights in every product of the
+backward pass (the bias and first-layer gradients stay unrounded).
 """
 from __future__ import annotations
 
@@ -125,11 +126,11 @@ def _backward(theta, x, fw, d_o, q):
     p = unpack(theta)
     z1, h1, z2, h2, _ = fw
     g = {}
-    g["W3"] = d_o.T @ q(h2)
+    g["W3"] = q(d_o).T @ q(h2)
     g["b3"] = d_o.sum(axis=0)
     dh2 = q(d_o) @ q(p["W3"])
     d2 = dh2 * gelu_grad(z2)
-    g["W2"] = d2.T @ q(h1)
+    g["W2"] = q(d2).T @ q(h1)
     g["b2"] = d2.sum(axis=0)
     dh1 = q(d2) @ q(p["W2"])
     d1 = dh1 * gelu_grad(z1)
