@@ -62,18 +62,21 @@ typedef struct {
     int32_t kernel;   /* rbm_kernel */
     int64_t n;        /* particles N, 2 <= N <= RBM_MAX_N */
     int32_t p;        /* batch size, 2 <= p <= N (p <= RBM_MAX_P_MULTI when N > one bucket) */
-    int32_t reserved; /* must be 0 */
+    int32_t cv;       /* 0: plain RBM-1 force; 1: learned control variate (d = 2,
+                         RBM_K_GAUSS, p <= RBM_MAX_P_CV; see cv_* below) */
     double kparam;    /* kernel softening a >= 0 */
     double beta;      /* external field coefficient: -grad V(x) = -beta x */
     double sigma;     /* noise amplitude sigma >= 0 */
     double dt;        /* time step tau > 0 */
     uint64_t seed;    /* Philox key */
     uint32_t sys;     /* Philox counter word 3 (system index in an ensemble) */
-    uint32_t reserved2; /* must be 0 */
+    uint32_t reserved; /* must be 0 */
 } rbm_params;
 
 #define RBM_MAX_N (1LL << 25)
 #define RBM_MAX_P_MULTI 64
+#define RBM_MAX_P_CV 64
+#define RBM_CV_NPARAM 6432 /* parameters of one control-variate network */
 
 typedef struct rbm_ctx rbm_ctx;
 
@@ -147,6 +150,54 @@ rbm_status rbm_phase_times(rbm_ctx *ctx, double *ms, int64_t *steps);
 
 /* Free the host context (not the workspace). */
 rbm_status rbm_destroy(rbm_ctx *ctx);
+
+/* ---- learned control variate (contexts created with cv = 1) -------------
+ * The batch force becomes (RBM-1 applied to the residual kernel, which Sec.
+ * 2.3 allows for general kernels K(x, y); unbiased for any weights by
+ * Lemma 3.1):
+ *   F_i = a(X_i).(S - c(X_i))/(N-1)
+ *         + 1/(s-1) sum_{j in batch, j != i} [K(X_i - X_j) - a(X_i).c(X_j)],
+ *   S = sum_j c(X_j) (FP64),
+ * with MLPs a, c: R^2 -> R^32 (2 -> 64 -> 64 -> 32, GELU after the hidden
+ * layers; outputs read as [component 2][rank 16]) evaluated with BF16 matrix
+ * instructions (FP32 accumulation).  Parameters of one net, FP32, in order:
+ * W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32]; a then c.
+ * rbm_init initialises them (cv_init with the context's seed). */
+
+/* Glorot-uniform weights (weight q of net n: (2u-1) sqrt(6/(fan_in+fan_out)),
+ * u from Philox(ctr = (q, n, 4, 0)), key = seed), zero biases, Adam state
+ * reset. */
+rbm_status cv_init(rbm_ctx *ctx, uint64_t seed, void *stream);
+
+/* Copy 2 x RBM_CV_NPARAM FP32 parameters in (resets the Adam state) / out. */
+rbm_status cv_set_weights(rbm_ctx *ctx, const float *d_w, void *stream);
+rbm_status cv_get_weights(rbm_ctx *ctx, float *d_w, void *stream);
+
+/* Network outputs of n points d_x [n][2]: d_a, d_c [n][32] (either may be
+ * NULL). */
+rbm_status cv_features(rbm_ctx *ctx, const float *d_x, int64_t n, float *d_a, float *d_c,
+                       void *stream);
+
+/* Loss L = 1/(2B) sum_pairs sum_k (K_k(x - y) - sum_r a_kr(x) c_kr(y))^2 over
+ * the B = npairs pairs (d_x[q], d_y[q]), and its gradient d_g [2][6432]
+ * (a then c).  d_loss: one float.  npairs <= 2^24. */
+rbm_status cv_grads(rbm_ctx *ctx, const float *d_x, const float *d_y, int64_t npairs,
+                    float *d_g, float *d_loss, void *stream);
+
+/* nsteps Adam steps (beta = (0.9, 0.999), eps = 1e-8, learning rate lr) on
+ * minibatches of `batch` pairs drawn from the nsnap snapshots d_snap
+ * [nsnap][N][2] (positions by id, e.g. saved with rbm_positions during a
+ * run): pair q of Adam step t (counted over the context's life) takes
+ * Philox(ctr = (q, t, 3, 0)) -> snapshot floor(w0 nsnap / 2^32), particle
+ * i = floor(w1 N / 2^32), j' = floor(w2 (N-1) / 2^32), j = j' + [j' >= i].
+ * d_loss: NULL or nsteps floats (the minibatch loss before each step). */
+rbm_status cv_train(rbm_ctx *ctx, const float *d_snap, int32_t nsnap, int64_t nsteps,
+                    int32_t batch, float lr, float *d_loss, void *stream);
+
+/* Measurement: d_out[0] = sum over t < nids of |d_f[d_ids[t]] - d_fref[t]|^2
+ * (d components each, FP64, fixed summation order).  d_f: [N][d] by id. */
+rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids,
+                           const float *d_fref, int32_t d, double *d_out, void *stream);
 
 /* Exact interaction force of eq. (1.2), F_i = 1/(N-1) sum_{j != i}
  * K(X_i - X_j), for the nids particles listed in d_ids (NULL: all N, in id

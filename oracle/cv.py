@@ -185,21 +185,41 @@ def adam(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 def cv_forces(theta_a, theta_c, x, perm, p, kfun=pair_kernel_gauss, use_bf16=False):
     """Control-variate batch forces for the division perm (ids in rank
-    order, batches as in RBM-1), x [N][2] by id."""
+    order, batches as in RBM-1), x [N][2] by id.  The batches of p (all but
+    the last) are evaluated together, one batch per row."""
     x = np.asarray(x, np.float64)
+    perm = np.asarray(perm, np.int64)
     n = x.shape[0]
     a = features(theta_a, x, use_bf16)     # [N][2][16]
     c = features(theta_c, x, use_bf16)
     S = c.sum(axis=0)                       # exact sum (FP64)
     f = np.einsum("ikr,ikr->ik", a, S[None] - c) / (n - 1)
     nb = n // p
-    for q in range(nb):
-        lo = q * p
-        hi = n if q == nb - 1 else lo + p
-        ids = np.asarray(perm[lo:hi], np.int64)
-        s = hi - lo
-        for i in ids:
-            others = ids[ids != i]
-            kres = kfun(x[i][None] - x[others]) - np.einsum("kr,jkr->jk", a[i], c[others])
-            f[i] += kres.sum(axis=0) / (s - 1)
+    groups = [perm[(nb - 1) * p:][None]]
+    if nb > 1:
+        groups.append(perm[:(nb - 1) * p].reshape(nb - 1, p))
+    for ids in groups:
+        nbat, s = ids.shape
+        xs = x[ids]                                           # [B][s][2]
+        dx = (xs[:, :, None, :] - xs[:, None, :, :]).reshape(-1, 2)
+        kv = kfun(dx).reshape(nbat, s, s, 2)                  # K(X_i - X_j)
+        ac = np.einsum("bikr,bjkr->bijk", a[ids], c[ids])     # a(X_i) . c(X_j)
+        res = kv - ac
+        res[:, np.arange(s), np.arange(s), :] = 0.0           # j != i
+        f[ids] += res.sum(axis=2) / (s - 1)
     return f
+
+
+def cv_step(theta_a, theta_c, prm, p, m, x, slots, kfun=pair_kernel_gauss, use_bf16=False):
+    """One RBM-1 step with the control-variate force (division and noise as
+    in the plain step of rbm_oracle.c).  Returns (x_new, slots_new)."""
+    from . import normals, permutation
+    x = np.asarray(x, np.float64)
+    perm = permutation(prm, m, slots)
+    f = cv_forces(theta_a, theta_c, x, perm, p, kfun, use_bf16)
+    n, d = x.shape
+    z = np.zeros((n, d))
+    if prm.sigma != 0.0:
+        z = np.array([normals(prm.seed, prm.sys, m, i)[:d] for i in range(n)])
+    x1 = x + prm.dt * (-prm.beta * x + f) + prm.sigma * math.sqrt(prm.dt) * z
+    return x1, perm

@@ -25,7 +25,10 @@ SYMBOLS = (
     "rbm_workspace_size", "rbm_init", "rbm_step", "rbm_run", "rbm_positions", "rbm_perm",
     "rbm_forces", "rbm_step_index", "rbm_check", "rbm_timing", "rbm_phase_times", "rbm_destroy",
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
+    "cv_init", "cv_set_weights", "cv_get_weights", "cv_features", "cv_grads", "cv_train",
+    "rbm_force_sqerr",
 )
+CV_NPARAM = 6432
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
 
@@ -37,9 +40,9 @@ class RbmError(RuntimeError):
 
 class rbm_params(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("kernel", ctypes.c_int32), ("n", ctypes.c_int64),
-                ("p", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kparam", ctypes.c_double),
+                ("p", ctypes.c_int32), ("cv", ctypes.c_int32), ("kparam", ctypes.c_double),
                 ("beta", ctypes.c_double), ("sigma", ctypes.c_double), ("dt", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("sys", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint64), ("sys", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -70,6 +73,13 @@ def lib():
         "rbm_destroy": [vp],
         "direct_forces": [pp, vp, vp, i64, vp, vp],
         "direct_step": [pp, vp, vp, i64, vp],
+        "cv_init": [vp, ctypes.c_uint64, vp],
+        "cv_set_weights": [vp, vp, vp],
+        "cv_get_weights": [vp, vp, vp],
+        "cv_features": [vp, vp, i64, vp, vp, vp],
+        "cv_grads": [vp, vp, vp, i64, vp, vp, vp],
+        "cv_train": [vp, vp, ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_float, vp, vp],
+        "rbm_force_sqerr": [vp, vp, i64, vp, ctypes.c_int32, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -115,9 +125,10 @@ class Params:
     dt: float = 1e-3
     seed: int = 1
     sys: int = 0
+    cv: int = 0
 
     def c(self) -> rbm_params:
-        return rbm_params(self.d, self.kernel, self.n, self.p, 0, self.kparam, self.beta,
+        return rbm_params(self.d, self.kernel, self.n, self.p, self.cv, self.kparam, self.beta,
                           self.sigma, self.dt, self.seed, self.sys, 0)
 
 
@@ -241,6 +252,73 @@ def direct_step(prm: Params, x, step: int, out=None, stream=None):
         out = torch.empty_like(x)
     _expect(out, torch.float32, (prm.n, prm.d), "out")
     _check(lib().direct_step(ctypes.byref(prm.c()), _ptr(x), _ptr(out), step, _stream(stream)))
+    return out
+
+
+# ---- control variate -------------------------------------------------------
+
+def cv_init(ctx: "Context", seed: int, stream=None):
+    _check(lib().cv_init(ctx.handle, seed, _stream(stream)))
+
+
+def cv_set_weights(ctx: "Context", w, stream=None):
+    import torch
+    _expect(w, torch.float32, (2, CV_NPARAM), "w")
+    _check(lib().cv_set_weights(ctx.handle, _ptr(w), _stream(stream)))
+
+
+def cv_get_weights(ctx: "Context", out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((2, CV_NPARAM), dtype=torch.float32, device=ctx.ws.device)
+    _expect(out, torch.float32, (2, CV_NPARAM), "out")
+    _check(lib().cv_get_weights(ctx.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def cv_features(ctx: "Context", x, stream=None):
+    """(a(x), c(x)), each [n][32]."""
+    import torch
+    n = x.shape[0]
+    _expect(x, torch.float32, (n, 2), "x")
+    a = torch.empty((n, 32), dtype=torch.float32, device=x.device)
+    c = torch.empty((n, 32), dtype=torch.float32, device=x.device)
+    _check(lib().cv_features(ctx.handle, _ptr(x), n, _ptr(a), _ptr(c), _stream(stream)))
+    return a, c
+
+
+def cv_grads(ctx: "Context", x, y, stream=None):
+    """(loss, gradient [2][6432]) on the pairs (x[q], y[q])."""
+    import torch
+    n = x.shape[0]
+    _expect(x, torch.float32, (n, 2), "x")
+    _expect(y, torch.float32, (n, 2), "y")
+    g = torch.empty((2, CV_NPARAM), dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().cv_grads(ctx.handle, _ptr(x), _ptr(y), n, _ptr(g), _ptr(loss), _stream(stream)))
+    return loss, g
+
+
+def cv_train(ctx: "Context", snap, nsteps: int, batch: int, lr: float = 1e-3, stream=None):
+    """nsteps Adam steps on pairs from snapshots snap [nsnap][N][2]; returns
+    the minibatch losses (before each step)."""
+    import torch
+    nsnap = snap.shape[0]
+    _expect(snap, torch.float32, (nsnap, ctx.prm.n, 2), "snap")
+    loss = torch.empty(max(nsteps, 1), dtype=torch.float32, device=snap.device)
+    _check(lib().cv_train(ctx.handle, _ptr(snap), nsnap, nsteps, batch, lr, _ptr(loss), _stream(stream)))
+    return loss[:nsteps]
+
+
+def rbm_force_sqerr(f, ids, fref, stream=None):
+    """sum_t |f[ids[t]] - fref[t]|^2 in FP64 (returns a 1-element CUDA tensor)."""
+    import torch
+    d = f.shape[1]
+    nids = ids.numel()
+    _expect(ids, torch.int32, (nids,), "ids")
+    _expect(fref, torch.float32, (nids, d), "fref")
+    out = torch.empty(1, dtype=torch.float64, device=f.device)
+    _check(lib().rbm_force_sqerr(_ptr(f), _ptr(ids), nids, _ptr(fref), d, _ptr(out), _stream(stream)))
     return out
 
 

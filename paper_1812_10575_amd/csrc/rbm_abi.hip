@@ -10,6 +10,7 @@
 #include <string>
 
 #include "../../include/rbm.h"
+#include "rbm_cv.hpp"
 #include "rbm_plan.hpp"
 
 using rbm::Plan;
@@ -23,6 +24,7 @@ struct rbm_ctx {
     void *ws;
     int64_t m;  // index of the next step
     bool pending;  // stored positions lack the noise of step m - 1
+    int64_t cv_t;  // Adam steps taken (the pair streams count them)
     // per-phase timing (measurement aid)
     hipEvent_t *ev;   // tmax * (RBM_NPHASES + 1) events
     int32_t tmax;     // steps the pool can record
@@ -67,8 +69,11 @@ rbm_status check_params(const rbm_params *prm)
                     (long long)RBM_MAX_N);
     if (prm->p < 2 || (int64_t)prm->p > prm->n)
         return fail(RBM_ERR_INVALID, "p = %d not in 2..N", prm->p);
-    if (prm->reserved != 0 || prm->reserved2 != 0)
-        return fail(RBM_ERR_INVALID, "reserved fields must be 0");
+    if (prm->reserved != 0) return fail(RBM_ERR_INVALID, "reserved field must be 0");
+    if (prm->cv != 0 && prm->cv != 1) return fail(RBM_ERR_INVALID, "cv must be 0 or 1");
+    if (prm->cv && (prm->d != 2 || prm->kernel != RBM_K_GAUSS || prm->p > RBM_MAX_P_CV))
+        return fail(RBM_ERR_UNSUPPORTED, "the control variate needs d = 2, the Gaussian kernel and p <= %d",
+                    RBM_MAX_P_CV);
     if (!(prm->dt > 0.0) || !std::isfinite(prm->dt)) return fail(RBM_ERR_INVALID, "dt must be > 0");
     if (!(prm->sigma >= 0.0) || !std::isfinite(prm->sigma))
         return fail(RBM_ERR_INVALID, "sigma must be >= 0");
@@ -136,6 +141,18 @@ Plan make_plan(const rbm_params *prm)
         pl.off_cstart = take((size_t)(pl.nb1 + 1) * 4);
         pl.off_ccur = take((size_t)pl.nb1 * 4);
     }
+    pl.cv = prm->cv;
+    if (pl.cv) {
+        pl.off_sorted = take(recs);
+        pl.off_cvmaster = take((size_t)2 * CV_NP * 4);
+        pl.off_cvam = take((size_t)2 * CV_NP * 4);
+        pl.off_cvav = take((size_t)2 * CV_NP * 4);
+        pl.off_cvwb = take((size_t)2 * CV_NB * 2);
+        pl.off_cvspart = take((size_t)CV_SUM_WG * CV_NO * 8);
+        pl.off_cvS = take((size_t)CV_NO * 8);
+        pl.off_cvgpart = take((size_t)CV_GRAD_WG * 2 * CV_NP * 4);
+        pl.off_cvlpart = take((size_t)CV_GRAD_WG * 4);
+    }
     pl.off_flags = take(256);
     pl.total = off;
     return pl;
@@ -171,6 +188,37 @@ rbm_status check_ctx(const rbm_ctx *ctx)
 }
 
 }  // namespace
+
+rbm_status check_cv(const rbm_ctx *ctx)
+{
+    rbm_status st = check_ctx(ctx);
+    if (st != RBM_OK) return st;
+    if (!ctx->plan.cv) return fail(RBM_ERR_INVALID, "context was created without cv = 1");
+    return RBM_OK;
+}
+
+template <typename T>
+T *wsp(const rbm_ctx *ctx, size_t off)
+{
+    return reinterpret_cast<T *>((char *)ctx->ws + off);
+}
+
+hipError_t zero_words(void *p, size_t nwords, hipStream_t st)
+{
+    return rbm::launch_fill(reinterpret_cast<uint32_t *>(p), nwords, 0u, st);
+}
+
+rbm_status cv_after_weights(rbm_ctx *ctx, hipStream_t st)
+{
+    const Plan &pl = ctx->plan;
+    hipError_t e = zero_words(wsp<float>(ctx, pl.off_cvam), 2 * CV_NP, st);
+    if (e == hipSuccess) e = zero_words(wsp<float>(ctx, pl.off_cvav), 2 * CV_NP, st);
+    if (e == hipSuccess) e = rbm::cv_launch_prep(wsp<float>(ctx, pl.off_cvmaster), wsp<__bf16>(ctx, pl.off_cvwb), st);
+    if (e != hipSuccess) return hip_fail(e, "control-variate set-up");
+    ctx->cv_t = 0;
+    return RBM_OK;
+}
+
 
 extern "C" {
 
@@ -224,6 +272,7 @@ rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_
         return hip_fail(e, "rbm_init launch");
     }
     *out = ctx;
+    if (pl.cv) return cv_init(ctx, prm->seed, stream);
     return RBM_OK;
 }
 
@@ -381,6 +430,104 @@ rbm_status rbm_destroy(rbm_ctx *ctx)
     if (ctx->ev) release_events(ctx);
     free(ctx);
     return RBM_OK;
+}
+
+rbm_status cv_init(rbm_ctx *ctx, uint64_t seed, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    hipError_t e = rbm::cv_launch_glorot(wsp<float>(ctx, ctx->plan.off_cvmaster), seed, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "cv_init");
+    return cv_after_weights(ctx, (hipStream_t)stream);
+}
+
+rbm_status cv_set_weights(rbm_ctx *ctx, const float *d_w, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    if (!d_w) return fail(RBM_ERR_INVALID, "d_w is NULL");
+    hipError_t e = hipMemcpyAsync(wsp<float>(ctx, ctx->plan.off_cvmaster), d_w, (size_t)2 * CV_NP * 4,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "cv_set_weights");
+    return cv_after_weights(ctx, (hipStream_t)stream);
+}
+
+rbm_status cv_get_weights(rbm_ctx *ctx, float *d_w, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    if (!d_w) return fail(RBM_ERR_INVALID, "d_w is NULL");
+    hipError_t e = hipMemcpyAsync(d_w, wsp<float>(ctx, ctx->plan.off_cvmaster), (size_t)2 * CV_NP * 4,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "cv_get_weights");
+}
+
+rbm_status cv_features(rbm_ctx *ctx, const float *d_x, int64_t n, float *d_a, float *d_c, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    if (!d_x || n < 0 || n > (1LL << 30)) return fail(RBM_ERR_INVALID, "bad points");
+    if (n == 0 || (!d_a && !d_c)) return RBM_OK;
+    hipError_t e = rbm::cv_launch_features(wsp<float>(ctx, ctx->plan.off_cvmaster), wsp<__bf16>(ctx, ctx->plan.off_cvwb),
+                                           d_x, (uint32_t)n, d_a, d_c, (hipStream_t)stream);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "cv_features");
+}
+
+rbm_status cv_grads(rbm_ctx *ctx, const float *d_x, const float *d_y, int64_t npairs, float *d_g,
+                    float *d_loss, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    if (!d_x || !d_y || !d_g || !d_loss) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (npairs < 1 || npairs > (1LL << 24)) return fail(RBM_ERR_INVALID, "npairs out of range");
+    const Plan &pl = ctx->plan;
+    uint32_t nwg = 0;
+    hipError_t e = rbm::cv_launch_grad((uint32_t)npairs, (float)ctx->prm.kparam, d_x, d_y, nullptr, 0, 0, 0,
+                                       ctx->prm.seed, wsp<float>(ctx, pl.off_cvmaster), wsp<__bf16>(ctx, pl.off_cvwb),
+                                       wsp<float>(ctx, pl.off_cvgpart), wsp<float>(ctx, pl.off_cvlpart), &nwg,
+                                       (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = rbm::cv_launch_reduce(nwg, wsp<float>(ctx, pl.off_cvgpart), wsp<float>(ctx, pl.off_cvlpart), d_g, d_loss,
+                                  0, 0.0f, 1, nullptr, nullptr, nullptr, (hipStream_t)stream);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "cv_grads");
+}
+
+rbm_status cv_train(rbm_ctx *ctx, const float *d_snap, int32_t nsnap, int64_t nsteps, int32_t batch, float lr,
+                    float *d_loss, void *stream)
+{
+    rbm_status st = check_cv(ctx);
+    if (st != RBM_OK) return st;
+    if (!d_snap || nsnap < 1 || nsteps < 0 || batch < 1 || batch > (1 << 24) || !(lr > 0.0f))
+        return fail(RBM_ERR_INVALID, "bad training arguments");
+    if (ctx->cv_t + nsteps > 0xffffffffLL) return fail(RBM_ERR_INVALID, "too many Adam steps");
+    const Plan &pl = ctx->plan;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        uint32_t nwg = 0;
+        hipError_t e = rbm::cv_launch_grad((uint32_t)batch, (float)ctx->prm.kparam, nullptr, nullptr, d_snap,
+                                           (uint32_t)nsnap, pl.n, (uint32_t)ctx->cv_t, ctx->prm.seed,
+                                           wsp<float>(ctx, pl.off_cvmaster), wsp<__bf16>(ctx, pl.off_cvwb),
+                                           wsp<float>(ctx, pl.off_cvgpart), wsp<float>(ctx, pl.off_cvlpart), &nwg,
+                                           (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = rbm::cv_launch_reduce(nwg, wsp<float>(ctx, pl.off_cvgpart), wsp<float>(ctx, pl.off_cvlpart), nullptr,
+                                      d_loss ? d_loss + k : nullptr, 1, lr, (int)(ctx->cv_t + 1),
+                                      wsp<float>(ctx, pl.off_cvmaster), wsp<float>(ctx, pl.off_cvam),
+                                      wsp<float>(ctx, pl.off_cvav), (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = rbm::cv_launch_prep(wsp<float>(ctx, pl.off_cvmaster), wsp<__bf16>(ctx, pl.off_cvwb), (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "cv_train");
+        ctx->cv_t += 1;
+    }
+    return RBM_OK;
+}
+
+rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids, const float *d_fref, int32_t d,
+                           double *d_out, void *stream)
+{
+    if (!d_f || !d_ids || !d_fref || !d_out) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (d < 1 || d > 3 || nids < 0 || nids > (1LL << 30)) return fail(RBM_ERR_INVALID, "bad sizes");
+    hipError_t e = rbm::launch_sqerr(d_f, d_ids, (uint32_t)nids, d_fref, d, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "rbm_force_sqerr");
 }
 
 rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t *d_ids,

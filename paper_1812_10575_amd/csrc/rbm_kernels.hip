@@ -29,6 +29,7 @@
 // by the unique key makes the result independent of it.  Up to 128 fine
 // buckets the split level is skipped (shift = 0); when N fits one
 // workgroup's LDS a single workgroup does the whole step in place.
+#include "rbm_cv.hpp"
 #include "rbm_device.hpp"
 #include "rbm_plan.hpp"
 
@@ -502,7 +503,8 @@ __device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *
 //      once, antisymmetric); P = 0, one thread per record.  Records of cut
 //      batches go to dst unchanged for k_fixup.
 // fout != nullptr: forces only (by id); dst gets only the cut batches.
-template <int D, int KERN, int P, bool SINGLE, int TPB, int CAP, int SBITS>
+// SORTONLY: every record is written to dst at its rank, nothing else.
+template <int D, int KERN, int P, bool SINGLE, int TPB, int CAP, int SBITS, bool SORTONLY = false>
 __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src,
                                                    const uint32_t *__restrict__ wsrc,
                                                    const uint32_t *__restrict__ bstart,
@@ -613,6 +615,12 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     }
     __syncthreads();
 
+    if constexpr (SORTONLY) {
+        // every record at its rank, unchanged (the control-variate path
+        // evaluates the batches from this order)
+        for (uint32_t l = tid; l < nb; l += TPB) dst[lo + l] = srec[pad(lo + l)];
+        return;
+    }
     // 5. batches.  The batches [bs, be) with lo <= bs and be <= hi are
     //    q_first..q_last; they cover ranks [ins_lo, ins_hi).  The last batch
     //    (q = nbat - 1) ends at n, so it is inside only if hi == n.
@@ -747,6 +755,31 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v)
     if (i < n) p[i] = v;
 }
 
+// out[0] = sum_t |f[ids[t]] - fref[t]|^2 in FP64: one workgroup, each thread
+// a strided FP64 partial, then a fixed-order tree.
+__global__ __launch_bounds__(1024) void k_sqerr(const float *__restrict__ f,
+                                                const uint32_t *__restrict__ ids, uint32_t nids,
+                                                const float *__restrict__ fref, int d,
+                                                double *__restrict__ out)
+{
+    __shared__ double part[1024];
+    double acc = 0.0;
+    for (uint32_t t = threadIdx.x; t < nids; t += 1024) {
+        const size_t i = ids[t];
+        for (int c = 0; c < d; ++c) {
+            const double e = (double)f[i * d + c] - (double)fref[(size_t)t * d + c];
+            acc += e * e;
+        }
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0];
+}
+
 // ---------------------------------------------------------------------------
 // direct sum: F_i = 1/(N-1) sum_{j != i} K(X_i - X_j), LDS tiles of j, FP32
 // pair terms summed per tile, FP64 across tiles.  step: apply the update.
@@ -835,6 +868,72 @@ T *at(void *ws, size_t off)
     return reinterpret_cast<T *>((char *)ws + off);
 }
 
+// Control-variate step (d = 2, Gaussian kernel): S = sum_j c(X_j) in FP64,
+// the same division as the plain step with the records written in rank
+// order, then the control-variate batch force and the drift update.
+hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, void *dst_state,
+                   float *fout, hipEvent_t *ev)
+{
+    auto *state = at<Rec<2>>(ws, pl.off_state);
+    auto *sorted = at<Rec<2>>(ws, pl.off_sorted);
+    auto *flags = at<uint32_t>(ws, pl.off_flags);
+    const float *master = at<float>(ws, pl.off_cvmaster);
+    const __bf16 *wb = at<__bf16>(ws, pl.off_cvwb);
+    double *S = at<double>(ws, pl.off_cvS);
+    mark(ev, 0, st);
+    hipError_t e = cv_launch_csum(s, state, master, wb, at<double>(ws, pl.off_cvspart), S, st);
+    if (e != hipSuccess) return e;
+    if (pl.nbuck == 1) {
+        for (int i = 1; i <= 5; ++i) mark(ev, i, st);
+        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
+                           dim3(1), dim3(SINGLE_TPB), 0, st, s, state, nullptr, nullptr, sorted,
+                           nullptr, flags);
+    } else {
+        auto *stage1 = at<Rec<2>>(ws, pl.off_stage1);
+        auto *w1 = at<uint32_t>(ws, pl.off_w1);
+        auto *fstart = at<uint32_t>(ws, pl.off_fstart);
+        auto *fcur = at<uint32_t>(ws, pl.off_fcur);
+        auto *cstart = at<uint32_t>(ws, pl.off_cstart);
+        auto *ccur = at<uint32_t>(ws, pl.off_ccur);
+        hipLaunchKernelGGL(k_key_count, dim3(pl.ntf), dim3(1024), (size_t)pl.nbuck * 4, st, s,
+                           pl.tilef, at<uint32_t>(ws, pl.off_kcnt));
+        mark(ev, 1, st);
+        hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256), dim3(256), 0, st, pl.ntf,
+                           pl.nbuck, at<uint32_t>(ws, pl.off_kcnt), at<uint32_t>(ws, pl.off_ftot));
+        mark(ev, 2, st);
+        hipLaunchKernelGGL(k_key_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift,
+                           pl.n, (uint32_t)SORT_CAP, at<uint32_t>(ws, pl.off_ftot), fstart, fcur,
+                           cstart, ccur, flags);
+        mark(ev, 3, st);
+        const Rec<2> *src = stage1;
+        const uint32_t *wsrc = w1;
+        if (pl.shift > 0) {
+            auto *stage2 = at<Rec<2>>(ws, pl.off_stage2);
+            auto *w2 = at<uint32_t>(ws, pl.off_w2);
+            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s,
+                               pl.shift, pl.nb1, state, ccur, stage1, w1);
+            mark(ev, 4, st);
+            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(LVL_TPB), 0, st, s,
+                               pl.shift, pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
+            src = stage2;
+            wsrc = w2;
+        } else {
+            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, 0u,
+                               pl.nbuck, state, fcur, stage1, w1);
+            mark(ev, 4, st);
+        }
+        mark(ev, 5, st);
+        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>),
+                           dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
+                           nullptr, flags);
+    }
+    mark(ev, 6, st);
+    e = cv_launch_batch(s, K_GAUSS, sorted, master, wb, S, dst_state, fout, st);
+    mark(ev, 7, st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 // The sort kernel specialised on the batch size (one thread per batch) for
 // the common sizes; any other p takes the one-thread-per-record form.
 template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB>
@@ -861,6 +960,9 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     auto *state = at<Rec<D>>(ws, pl.off_state);
     auto *dst = reinterpret_cast<Rec<D> *>(dst_state);
     auto *flags = at<uint32_t>(ws, pl.off_flags);
+    if constexpr (D == 2 && KERN == K_GAUSS) {
+        if (pl.cv) return step_cv(pl, s, ws, st, dst_state, fout, ev);
+    }
     if (pl.nbuck == 1) {
         for (int i = 0; i <= 5; ++i) mark(ev, i, st);
         launch_sort<D, KERN, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS>(
@@ -984,6 +1086,19 @@ hipError_t launch_positions(const Plan &pl, const StepArgs &s, int d, const void
     case 2: hipLaunchKernelGGL(k_positions<2>, g, dim3(256), 0, st, s, (const Rec<2> *)state, x, ids); break;
     default: hipLaunchKernelGGL(k_positions<3>, g, dim3(256), 0, st, s, (const Rec<3> *)state, x, ids); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, p, (uint32_t)n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqerr(const float *f, const uint32_t *ids, uint32_t nids, const float *fref, int d,
+                        double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sqerr, dim3(1), dim3(1024), 0, st, f, ids, nids, fref, d, out);
     return hipGetLastError();
 }
 

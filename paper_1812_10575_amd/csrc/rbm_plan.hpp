@@ -40,6 +40,10 @@ struct Plan {
     size_t rec_bytes;
     size_t off_state, off_scratch, off_stage1, off_w1, off_stage2, off_w2;
     size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;
+    // control variate (cv != 0)
+    int cv;
+    size_t off_sorted, off_cvmaster, off_cvam, off_cvav, off_cvwb, off_cvspart, off_cvS;
+    size_t off_cvgpart, off_cvlpart, off_cvgrad, off_cvloss;
     size_t total;
 };
 
@@ -50,6 +54,9 @@ hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *s
 // x != NULL: positions by id, with the pending noise of s added.
 hipError_t launch_positions(const Plan &pl, const StepArgs &s, int d, const void *ws, float *x,
                             uint32_t *ids, hipStream_t st);
+hipError_t launch_fill(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_sqerr(const float *f, const uint32_t *ids, uint32_t nids, const float *fref, int d,
+                        double *out, hipStream_t st);
 hipError_t launch_direct(const StepArgs &s, int d, int kernel, const float *x,
                          const uint32_t *ids, uint32_t nids, float *out, int step,
                          hipStream_t st);

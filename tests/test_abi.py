@@ -50,6 +50,9 @@ def test_workspace_size_grows_with_n():
     (dict(d=0), rbm.RBM_ERR_INVALID),
     (dict(d=4), rbm.RBM_ERR_INVALID),
     (dict(kernel=7), rbm.RBM_ERR_INVALID),
+    (dict(cv=2), rbm.RBM_ERR_INVALID),
+    (dict(cv=1), rbm.RBM_ERR_UNSUPPORTED),
+    (dict(cv=1, d=2, kernel=rbm.RBM_K_GAUSS, p=65), rbm.RBM_ERR_UNSUPPORTED),
     (dict(n=1, p=2), rbm.RBM_ERR_INVALID),
     (dict(p=1), rbm.RBM_ERR_INVALID),
     (dict(n=100, p=101), rbm.RBM_ERR_INVALID),

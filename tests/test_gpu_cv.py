@@ -1,0 +1,212 @@
+"""GPU parity of the learned control variate (BF16 matrix instructions,
+FP32 accumulation) against the FP64 oracle that rounds the same operands to
+BF16, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as ora
+import rbm_inputs
+from oracle import cv
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1812_10575_amd as rbm  # noqa: E402
+
+FIELDS = ("d", "kernel", "n", "p", "kparam", "beta", "sigma", "dt", "seed")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def wl(**over):
+    return rbm_inputs.params_of("gauss2d-n1024-p2", **over)
+
+
+def gp(w, cvf=1):
+    return rbm.Params(**{k: w[k] for k in FIELDS}, cv=cvf)
+
+
+def op(w):
+    return ora.Params(d=w["d"], kernel=w["kernel"], kparam=w["kparam"], beta=w["beta"],
+                      sigma=w["sigma"], dt=w["dt"], seed=w["seed"])
+
+
+def thetas(seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for net in range(2):
+        th = cv.glorot_init(net, seed=seed)
+        p = cv.unpack(th)
+        for b in ("b1", "b2", "b3"):
+            p[b][...] = 0.3 * rng.standard_normal(p[b].shape)
+        out.append(th.astype(np.float32).astype(np.float64))
+    return out
+
+
+def ctx_with(w, ta=None, tc=None, x0=None):
+    x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"]) if x0 is None else x0
+    ctx = rbm.rbm_init(gp(w), torch.from_numpy(np.ascontiguousarray(x0)).cuda())
+    if ta is not None:
+        rbm.cv_set_weights(ctx, torch.from_numpy(np.stack([ta, tc]).astype(np.float32)).cuda())
+    return ctx, x0
+
+
+def test_glorot_init_matches_oracle():
+    w = wl(n=256)
+    ctx, _ = ctx_with(w)
+    got = rbm.cv_get_weights(ctx).cpu().numpy().astype(np.float64)
+    for net in range(2):
+        want = cv.glorot_init(net, seed=w["seed"])
+        np.testing.assert_allclose(got[net], want, rtol=2e-7, atol=1e-7)
+
+
+def test_features_match_oracle():
+    ta, tc = thetas()
+    w = wl(n=256)
+    ctx, _ = ctx_with(w, ta, tc)
+    x = rbm_inputs.normal(1000, 2, seed=5) * 1.5
+    a, c = rbm.cv_features(ctx, torch.from_numpy(x).cuda())
+    a, c = a.cpu().numpy(), c.cpu().numpy()
+    for got, th in ((a, ta), (c, tc)):
+        want = cv.forward(th, x.astype(np.float64), use_bf16=True)[4]
+        err = np.abs(got - want)
+        scale = max(1.0, float(np.max(np.abs(want))))
+        say("features max err", err.max() / scale, "rms", math.sqrt(np.mean(err ** 2)) / scale)
+        assert err.max() / scale < 5e-3
+        assert math.sqrt(np.mean(err ** 2)) / scale < 2e-4
+
+
+@pytest.mark.parametrize("npairs", [64, 300, 4096])
+def test_loss_and_gradients_match_oracle(npairs):
+    ta, tc = thetas(7)
+    w = wl(n=256)
+    ctx, _ = ctx_with(w, ta, tc)
+    rng = np.random.default_rng(npairs)
+    x = rng.standard_normal((npairs, 2)).astype(np.float32)
+    y = (x + 0.7 * rng.standard_normal((npairs, 2))).astype(np.float32)
+    loss, g = rbm.cv_grads(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
+    loss, g = float(loss.cpu()[0]), g.cpu().numpy().astype(np.float64)
+    lo, ga, gc = cv.loss_and_grads(ta, tc, x.astype(np.float64), y.astype(np.float64), use_bf16=True)
+    say("loss", loss, lo)
+    assert loss == pytest.approx(lo, rel=2e-3)
+    for got, want in ((g[0], ga), (g[1], gc)):
+        scale = float(np.max(np.abs(want)))
+        err = np.abs(got - want) / scale
+        say("grad max err", err.max(), "rms", math.sqrt(np.mean(err ** 2)))
+        assert err.max() < 1e-2
+        assert math.sqrt(np.mean(err ** 2)) < 1e-3
+        # every parameter block agrees in direction
+        assert np.dot(got, want) / (np.linalg.norm(got) * np.linalg.norm(want)) > 0.9999
+
+
+def test_training_sampler_and_adam_match_oracle():
+    """The first minibatch loss of cv_train equals the oracle's loss on the
+    pairs the oracle's sampler draws; one Adam step applied to the GPU's own
+    gradient gives the oracle's update."""
+    w = wl(n=500)
+    ta, tc = thetas(11)
+    ctx, x0 = ctx_with(w, ta, tc)
+    rng = np.random.default_rng(0)
+    snap = np.stack([x0, x0 + 0.1 * rng.standard_normal(x0.shape).astype(np.float32)]).astype(np.float32)
+    batch = 256
+    pr = cv.sample_pairs(0, batch, 2, w["n"], seed=w["seed"])
+    xs = snap[pr[:, 0], pr[:, 1]].astype(np.float64)
+    ys = snap[pr[:, 0], pr[:, 2]].astype(np.float64)
+    lo, ga, gc = cv.loss_and_grads(ta, tc, xs, ys, use_bf16=True)
+    _, g_gpu = rbm.cv_grads(ctx, torch.from_numpy(xs.astype(np.float32)).cuda(),
+                            torch.from_numpy(ys.astype(np.float32)).cuda())
+    g_gpu = g_gpu.cpu().numpy().astype(np.float64)
+    losses = rbm.cv_train(ctx, torch.from_numpy(snap).cuda(), 1, batch, lr=1e-3).cpu().numpy()
+    assert losses[0] == pytest.approx(lo, rel=2e-3)
+    w1 = rbm.cv_get_weights(ctx).cpu().numpy().astype(np.float64)
+    for net, th in ((0, ta), (1, tc)):
+        want, _, _ = cv.adam(th, g_gpu[net], np.zeros(cv.NPARAM), np.zeros(cv.NPARAM), 1, lr=1e-3)
+        np.testing.assert_allclose(w1[net], want, rtol=1e-5, atol=2e-6)
+
+
+@pytest.mark.parametrize("n,p", [(1024, 2), (5000, 2), (20011, 4), (140000, 8)])
+def test_cv_forces_match_oracle(n, p):
+    w = wl(n=n, p=p)
+    ta, tc = thetas(13)
+    ctx, x0 = ctx_with(w, ta, tc)
+    rbm.rbm_run(ctx, 2)
+    x = rbm.rbm_positions(ctx).cpu().numpy()
+    s = rbm.rbm_perm(ctx).cpu().numpy().view(np.uint32)
+    o = op(w)
+    for m in (2, 5):
+        f = rbm.rbm_forces(ctx, m).cpu().numpy()
+        perm = ora.permutation(o, m, s)
+        fo = cv.cv_forces(ta, tc, x.astype(np.float64), perm, p, use_bf16=True)
+        scale = max(1.0, float(np.max(np.abs(fo))))
+        err = np.abs(f - fo) / scale
+        say(n, p, m, "cv force max err", err.max(), "rms", math.sqrt(np.mean(err ** 2)))
+        assert err.max() < 5e-3
+        assert math.sqrt(np.mean(err ** 2)) < 3e-4
+
+
+def test_cv_step_matches_oracle():
+    w = wl(n=3000, p=2)
+    ta, tc = thetas(17)
+    ctx, x0 = ctx_with(w, ta, tc)
+    o = op(w)
+    for m in range(3):
+        xm = rbm.rbm_positions(ctx).cpu().numpy()
+        sm = rbm.rbm_perm(ctx).cpu().numpy().view(np.uint32)
+        rbm.rbm_step(ctx)
+        x1 = rbm.rbm_positions(ctx).cpu().numpy()
+        s1 = rbm.rbm_perm(ctx).cpu().numpy().view(np.uint32)
+        xo, so = cv.cv_step(ta, tc, o, w["p"], m, xm.astype(np.float64), sm, use_bf16=True)
+        assert np.array_equal(s1, so)
+        assert ora.rel_max_error(x1, xo) < 1e-5
+
+
+def test_cv_force_is_unbiased_on_the_gpu():
+    """Averaged over R divisions the control-variate force approaches the
+    direct force at the rate of its own spread (Lemma 3.1 for K_res)."""
+    n, p, R = 4096, 2, 64
+    w = wl(n=n, p=p)
+    ta, tc = thetas(19)
+    ctx, x0 = ctx_with(w, ta, tc)
+    fs = np.stack([rbm.rbm_forces(ctx, m).cpu().numpy() for m in range(R)])
+    fd = ora.direct_forces(op(w), x0.astype(np.float64))
+    mean = fs.mean(axis=0)
+    sd = fs.std(axis=0) / math.sqrt(R) + 1e-6
+    z = np.abs(mean - fd) / sd
+    assert np.mean(z) < 1.2 and np.quantile(z, 0.999) < 5.5
+
+
+def test_trained_network_beats_plain_rbm():
+    """Train on pairs from the run's own trajectory (plain RBM-1), then the
+    force MSE against the direct sum, averaged over divisions, is smaller
+    with the control variate than without it at the same p."""
+    n, p = 1 << 15, 2
+    w = wl(n=n, p=p)
+    plain = rbm.rbm_init(gp(w, 0), torch.from_numpy(rbm_inputs.workload(w["init"], n, w["seed"])).cuda())
+    snaps = []
+    for k in range(8):
+        rbm.rbm_run(plain, 25)
+        snaps.append(rbm.rbm_positions(plain).clone())
+    snap = torch.stack(snaps)
+    x = snaps[-1]
+    ctx = rbm.rbm_init(gp(w, 1), x)
+    losses = rbm.cv_train(ctx, snap, 400, 4096, lr=2e-3).cpu().numpy()
+    say("loss", losses[:3], losses[-3:])
+    assert losses[-20:].mean() < 0.25 * losses[:20].mean()
+    ids = torch.from_numpy(np.random.default_rng(0).choice(n, 2048, replace=False).astype(np.int32)).cuda()
+    fdir = rbm.direct_forces(gp(w, 0), x, ids)
+    mse = {}
+    for name, c in (("plain", rbm.rbm_init(gp(w, 0), x)), ("cv", ctx)):
+        acc = 0.0
+        for m in range(16):
+            f = rbm.rbm_forces(c, 1000 + m)
+            acc += float(rbm.rbm_force_sqerr(f, ids, fdir).cpu()[0])
+        mse[name] = acc / (16 * ids.numel())
+    say("force MSE", mse, "gain", mse["plain"] / mse["cv"])
+    assert mse["cv"] < 0.5 * mse["plain"]
