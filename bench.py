@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -54,6 +55,76 @@ def cpu_baseline(w: dict, x0) -> dict:
                       f"single-threaded FP64 C oracle, {t:.1f} s"}
 
 
+def force_mse(args) -> dict:
+    """Force MSE against the direct sum, plain RBM-1 vs the learned control
+    variate, on the Gaussian workload at N = 2^22, p = 2.  The networks are
+    trained on pairs drawn from 16 snapshots of the run's own plain
+    trajectory; the MSE is averaged over 16 divisions on a fixed subset of
+    2^16 particles whose exact forces come from the direct sum."""
+    import numpy as np
+    import torch
+
+    import paper_1812_10575_amd as rbm
+    import rbm_inputs
+
+    w = rbm_inputs.params_of("gauss2d-n2^22-p2")
+    n = w["n"]
+    mk = lambda **o: rbm.Params(**{k: o.get(k, w[k]) for k in FIELDS}, cv=o.get("cv", 0))
+    x0 = torch.from_numpy(rbm_inputs.workload(w["init"], n, w["seed"])).cuda()
+    plain = rbm.rbm_init(mk(), x0)
+    snaps = []
+    for _ in range(16):
+        rbm.rbm_run(plain, args.mse_snap_every)
+        snaps.append(rbm.rbm_positions(plain).clone())
+    snap = torch.stack(snaps)
+    x = snaps[-1]
+    cvctx = rbm.rbm_init(mk(cv=1), x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = rbm.cv_train(cvctx, snap, args.train_steps, args.train_batch, lr=args.lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ids = torch.from_numpy(np.random.default_rng(7).choice(n, 1 << 16, replace=False).astype(np.int32)).cuda()
+    fdir = rbm.direct_forces(mk(), x, ids)
+
+    def mse_of(ctx):
+        acc = 0.0
+        for m in range(16):
+            f = rbm.rbm_forces(ctx, 100000 + m)
+            acc += float(rbm.rbm_force_sqerr(f, ids, fdir).cpu()[0])
+        return acc / (16 * ids.numel())
+
+    def rate_of(ctx, steps=20):
+        rbm.rbm_run(ctx, 3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rbm.rbm_run(ctx, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return n * steps / (e0.elapsed_time(e1) * 1e-3)
+
+    mse_plain = mse_of(rbm.rbm_init(mk(), x))
+    mse_cv = mse_of(cvctx)
+    gain = mse_plain / mse_cv
+    # Lemma 3.1: MSE(p) = (1/(p-1) - 1/(N-1)) Lambda, so equal MSE needs
+    # 1/(p'-1) - 1/(N-1) = (1 - 1/(N-1)) / gain
+    pp = int(math.ceil(1.0 + 1.0 / ((1.0 - 1.0 / (n - 1)) / gain + 1.0 / (n - 1))))
+    pp = max(2, min(pp, 64))
+    plain_pp = rbm.rbm_init(mk(p=pp), x)
+    mse_pp = mse_of(plain_pp)
+    out = {"workload": "gauss2d-n2^22-p2", "n": n, "p": 2, "subset": int(ids.numel()), "divisions": 16,
+           "mse_plain": mse_plain, "mse_cv": mse_cv, "gain": gain,
+           "train": {"pairs": args.train_steps * args.train_batch, "adam_steps": args.train_steps,
+                     "batch": args.train_batch, "seconds": round(t_train, 3),
+                     "loss_first": float(losses[:16].mean().cpu()), "loss_last": float(losses[-16:].mean().cpu())},
+           "equal_mse": {"p_plain": pp, "mse_plain": mse_pp,
+                         "plain_particle_steps_per_s": rate_of(plain_pp),
+                         "cv_particle_steps_per_s": rate_of(cvctx),
+                         "plain_p2_particle_steps_per_s": rate_of(rbm.rbm_init(mk(), x))}}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +133,11 @@ def main() -> int:
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mse", action="store_true", help="skip the plain vs control-variate MSE part")
+    ap.add_argument("--train-steps", type=int, default=4096)
+    ap.add_argument("--train-batch", type=int, default=16384)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--mse-snap-every", type=int, default=25)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -138,6 +214,8 @@ def main() -> int:
                    "a": w["kparam"], "beta": w["beta"], "sigma": w["sigma"], "dt": w["dt"]},
         "roofline": roof,
     }
+    if not args.no_mse:
+        out["force_mse"] = force_mse(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

@@ -71,6 +71,9 @@ WORKLOADS = {
     # 1-D softened Coulomb (eps = 1e-3) in a harmonic trap, no noise
     "dyson1d-n2^20-p2": dict(d=1, kernel=1, n=1 << 20, p=2, kparam=1e-6, beta=1.0, sigma=0.0,
                              dt=1e-4, seed=1, init="dyson1d", steps=100000),
+    # the Gaussian workload at 2^22 particles (control-variate comparison)
+    "gauss2d-n2^22-p2": dict(d=2, kernel=0, n=1 << 22, p=2, kparam=0.0, beta=1.0, sigma=0.5,
+                             dt=1e-3, seed=1, init="gauss2d", steps=1000),
     # 3-D attraction-repulsion, free space, weak noise
     "attrep3d-n2^24-p8": dict(d=3, kernel=2, n=1 << 24, p=8, kparam=0.01, beta=0.0, sigma=0.1,
                               dt=1e-3, seed=1, init="attrep3d", steps=100),
