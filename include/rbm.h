@@ -199,6 +199,52 @@ rbm_status cv_train(rbm_ctx *ctx, const float *d_snap, int32_t nsnap, int64_t ns
 rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids,
                            const float *d_fref, int32_t d, double *d_out, void *stream);
 
+/* ---- batched ensemble -----------------------------------------------------
+ * nsys independent RBM-1 systems sharing the model parameters, system s with
+ * N_s particles, Philox key seed_s and counter word 3 = s: each follows the
+ * definitions of a standalone run with those values (its division is the
+ * standalone one bit for bit).  All systems run in one persistent launch:
+ * workgroups take systems from a queue ordered by decreasing N_s.  Systems
+ * of up to tile.lds_max particles (<= RBM_ENS_LDS) stay in LDS for all
+ * steps; larger ones (up to RBM_ENS_MAXN) are streamed through the
+ * workspace. */
+typedef struct {
+    int32_t d;        /* space dimension: 2 */
+    int32_t kernel;   /* rbm_kernel */
+    int32_t p;        /* batch size, 2 <= p <= min N_s, p <= RBM_MAX_P_MULTI */
+    int32_t reserved; /* must be 0 */
+    double kparam, beta, sigma, dt;  /* as in rbm_params */
+    int64_t nsys;     /* number of systems, >= 1 */
+} rbm_ensemble;
+
+/* Launch shape (the autotuner's search space); zeros select the defaults. */
+typedef struct {
+    int32_t lds_max;  /* systems up to this size stay in LDS (<= RBM_ENS_LDS) */
+    int32_t grid;     /* persistent workgroups (default: one per compute unit) */
+} rbm_ensemble_tile;
+
+#define RBM_ENS_LDS 4096
+#define RBM_ENS_MAXN (256 * 1024)
+
+/* Workspace bytes for these systems (a 256-byte aligned device buffer of
+ * about 28 bytes per particle plus the system table); h_n: host array of nsys
+ * sizes.  Errors: RBM_ERR_INVALID for a size outside p..RBM_ENS_MAXN,
+ * RBM_ERR_UNSUPPORTED for d != 2 or more than 2^31 - 1 particles in all. */
+rbm_status ensemble_workspace_size(const rbm_ensemble *e, const int64_t *h_n, size_t *bytes);
+
+/* Runs steps step0 .. step0 + nsteps - 1 of every system.  Each call starts
+ * every system with slot k holding particle k (as rbm_init with no slots at
+ * step step0), so one call of 2k steps and two calls of k steps differ in
+ * their divisions.  h_n, h_seed: host arrays of nsys sizes and Philox keys.  d_x: packed FP32 positions
+ * [sum N_s][d], system by system, each by particle id; read at the start and
+ * overwritten with the final positions.  graph != 0: the launch is recorded
+ * into a hipGraph and replayed once.  Waits for completion and returns
+ * RBM_ERR_DEVICE if a device-side check failed. */
+rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_t *h_seed,
+                        float *d_x, int64_t step0, int64_t nsteps,
+                        const rbm_ensemble_tile *tile, void *d_ws, size_t ws_bytes,
+                        int32_t graph, void *stream);
+
 /* Exact interaction force of eq. (1.2), F_i = 1/(N-1) sum_{j != i}
  * K(X_i - X_j), for the nids particles listed in d_ids (NULL: all N, in id
  * order).  d_x: [N][d] by id; d_f: [nids][d].  FP32 pair terms, FP64 sums. */

@@ -26,8 +26,10 @@ SYMBOLS = (
     "rbm_forces", "rbm_step_index", "rbm_check", "rbm_timing", "rbm_phase_times", "rbm_destroy",
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
     "cv_init", "cv_set_weights", "cv_get_weights", "cv_features", "cv_grads", "cv_train",
-    "rbm_force_sqerr",
+    "rbm_force_sqerr", "ensemble_workspace_size", "ensemble_run",
 )
+ENS_LDS = 4096
+ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
@@ -43,6 +45,16 @@ class rbm_params(ctypes.Structure):
                 ("p", ctypes.c_int32), ("cv", ctypes.c_int32), ("kparam", ctypes.c_double),
                 ("beta", ctypes.c_double), ("sigma", ctypes.c_double), ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("sys", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class rbm_ensemble(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("kernel", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("kparam", ctypes.c_double), ("beta", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("dt", ctypes.c_double), ("nsys", ctypes.c_int64)]
+
+
+class rbm_ensemble_tile(ctypes.Structure):
+    _fields_ = [("lds_max", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,6 +92,9 @@ def lib():
         "cv_grads": [vp, vp, vp, i64, vp, vp, vp],
         "cv_train": [vp, vp, ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_float, vp, vp],
         "rbm_force_sqerr": [vp, vp, i64, vp, ctypes.c_int32, vp, vp],
+        "ensemble_workspace_size": [ctypes.POINTER(rbm_ensemble), vp, ctypes.POINTER(sz)],
+        "ensemble_run": [ctypes.POINTER(rbm_ensemble), vp, vp, vp, i64, i64,
+                         ctypes.POINTER(rbm_ensemble_tile), vp, sz, ctypes.c_int32, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -320,6 +335,69 @@ def rbm_force_sqerr(f, ids, fref, stream=None):
     out = torch.empty(1, dtype=torch.float64, device=f.device)
     _check(lib().rbm_force_sqerr(_ptr(f), _ptr(ids), nids, _ptr(fref), d, _ptr(out), _stream(stream)))
     return out
+
+
+# --------------------------------------------------------------------------
+# batched ensemble
+
+
+@dataclass
+class Ensemble:
+    """Independent RBM-1 systems sharing the model parameters; system s has
+    sizes[s] particles and Philox key seeds[s] (counter word 3 = s)."""
+    d: int
+    kernel: int
+    p: int
+    sizes: object
+    seeds: object
+    kparam: float = 0.0
+    beta: float = 0.0
+    sigma: float = 0.0
+    dt: float = 1e-3
+
+    def c(self) -> rbm_ensemble:
+        return rbm_ensemble(self.d, self.kernel, self.p, 0, self.kparam, self.beta, self.sigma, self.dt,
+                            len(self.sizes))
+
+    def host_arrays(self):
+        import numpy as np
+        n = np.ascontiguousarray(self.sizes, dtype=np.int64)
+        sd = np.ascontiguousarray(self.seeds, dtype=np.uint64)
+        if n.shape != sd.shape or n.ndim != 1:
+            raise ValueError("sizes and seeds must be 1-D arrays of equal length")
+        return n, sd
+
+    @property
+    def offsets(self):
+        import numpy as np
+        n = np.asarray(self.sizes, dtype=np.int64)
+        return np.concatenate([[0], np.cumsum(n)])
+
+
+def ensemble_workspace_size(ens: Ensemble) -> int:
+    n, _ = ens.host_arrays()
+    out = ctypes.c_size_t()
+    _check(lib().ensemble_workspace_size(ctypes.byref(ens.c()), n.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+    return out.value
+
+
+def ensemble_run(ens: Ensemble, x, step0: int, nsteps: int, lds_max: int = 0, grid: int = 0,
+                 graph: bool = True, ws=None, stream=None):
+    """Runs steps step0 .. step0 + nsteps - 1 of every system in place on x
+    [sum sizes][d] (FP32, system by system, each by particle id).  Returns
+    when the launch has completed."""
+    import torch
+    n, sd = ens.host_arrays()
+    tot = int(n.sum())
+    _expect(x, torch.float32, (tot, ens.d), "x")
+    need = ensemble_workspace_size(ens)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    tile = rbm_ensemble_tile(lds_max, grid)
+    _check(lib().ensemble_run(ctypes.byref(ens.c()), n.ctypes.data_as(ctypes.c_void_p),
+                              sd.ctypes.data_as(ctypes.c_void_p), _ptr(x), step0, nsteps, ctypes.byref(tile),
+                              _ptr(ws), ws.numel(), 1 if graph else 0, _stream(stream)))
+    return x
 
 
 def _expect(t, dtype, shape, name):

@@ -10,7 +10,12 @@
 #include <string>
 
 #include "../../include/rbm.h"
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
 #include "rbm_cv.hpp"
+#include "rbm_ensemble.hpp"
 #include "rbm_plan.hpp"
 
 using rbm::Plan;
@@ -561,6 +566,186 @@ rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out, 
     hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, nullptr, (uint32_t)prm->n,
                                       d_x_out, 1, (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_step launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched ensemble
+// ---------------------------------------------------------------------------
+
+static_assert(RBM_ENS_LDS == 4096 && RBM_ENS_MAXN == 256 * 1024, "ensemble limits of the header and the kernels differ");
+
+namespace {
+
+struct EnsLayout {
+    size_t sys, order, ctl, state, stage, wst, total;
+    uint64_t nsum;
+};
+
+rbm_status ens_check(const rbm_ensemble *e, const int64_t *h_n, EnsLayout *lay)
+{
+    if (!e || !h_n) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (e->d != 2) return fail(RBM_ERR_UNSUPPORTED, "the ensemble kernels implement d = 2 (got %d)", e->d);
+    if (e->kernel < RBM_K_GAUSS || e->kernel > RBM_K_ATTREP) return fail(RBM_ERR_INVALID, "unknown kernel %d", e->kernel);
+    if (e->reserved != 0) return fail(RBM_ERR_INVALID, "reserved field must be 0");
+    if (e->nsys < 1 || e->nsys > (1LL << 24)) return fail(RBM_ERR_INVALID, "nsys = %lld not in 1..2^24", (long long)e->nsys);
+    if (e->p < 2 || e->p > RBM_MAX_P_MULTI) return fail(RBM_ERR_INVALID, "p = %d not in 2..%d", e->p, RBM_MAX_P_MULTI);
+    if (!(e->dt > 0.0) || !std::isfinite(e->dt)) return fail(RBM_ERR_INVALID, "dt must be > 0");
+    if (!(e->sigma >= 0.0) || !std::isfinite(e->sigma)) return fail(RBM_ERR_INVALID, "sigma must be >= 0");
+    if (!(e->kparam >= 0.0) || !std::isfinite(e->kparam)) return fail(RBM_ERR_INVALID, "kparam must be >= 0");
+    if (!std::isfinite(e->beta)) return fail(RBM_ERR_INVALID, "beta must be finite");
+    uint64_t nsum = 0;
+    for (int64_t i = 0; i < e->nsys; ++i) {
+        if (h_n[i] < e->p || h_n[i] > RBM_ENS_MAXN)
+            return fail(RBM_ERR_INVALID, "system %lld: N = %lld not in p..%d", (long long)i, (long long)h_n[i],
+                        RBM_ENS_MAXN);
+        nsum += (uint64_t)h_n[i];
+    }
+    if (nsum > 0x7fffffffULL) return fail(RBM_ERR_UNSUPPORTED, "%llu particles in all, above 2^31 - 1", (unsigned long long)nsum);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    lay->nsum = nsum;
+    lay->sys = take((size_t)e->nsys * sizeof(rbm::EnsSys));
+    lay->order = take((size_t)e->nsys * 4);
+    lay->ctl = take(8);
+    lay->state = take(nsum * sizeof(rbm::Rec<2>));
+    lay->stage = take(nsum * sizeof(rbm::Rec<2>));
+    lay->wst = take(nsum * 4);
+    lay->total = off;
+    return RBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbm_status ensemble_workspace_size(const rbm_ensemble *e, const int64_t *h_n, size_t *bytes)
+{
+    EnsLayout lay;
+    rbm_status st = ens_check(e, h_n, &lay);
+    if (st != RBM_OK) return st;
+    if (!bytes) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    *bytes = lay.total;
+    return RBM_OK;
+}
+
+rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_t *h_seed, float *d_x,
+                        int64_t step0, int64_t nsteps, const rbm_ensemble_tile *tile, void *d_ws,
+                        size_t ws_bytes, int32_t graph, void *stream)
+{
+    EnsLayout lay;
+    rbm_status st = ens_check(e, h_n, &lay);
+    if (st != RBM_OK) return st;
+    if (!h_seed || !d_x || !d_ws) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (ws_bytes < lay.total)
+        return fail(RBM_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, lay.total);
+    if (((uintptr_t)d_ws & 255) != 0) return fail(RBM_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (step0 < 0 || nsteps < 0 || step0 + nsteps > 0x100000000LL)
+        return fail(RBM_ERR_INVALID, "steps out of range");
+    if (graph != 0 && graph != 1) return fail(RBM_ERR_INVALID, "graph must be 0 or 1");
+    int lds_max = tile ? tile->lds_max : 0;
+    int grid = tile ? tile->grid : 0;
+    if (lds_max == 0) lds_max = RBM_ENS_LDS;
+    if (lds_max < 0 || lds_max > RBM_ENS_LDS) return fail(RBM_ERR_INVALID, "lds_max = %d not in 0..%d", lds_max, RBM_ENS_LDS);
+    if (grid < 0 || grid > 65536) return fail(RBM_ERR_INVALID, "grid = %d not in 0..65536", grid);
+    if (grid == 0) {
+        int dev = 0, cus = 0;
+        hipError_t he = hipGetDevice(&dev);
+        if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (he != hipSuccess) return hip_fail(he, "compute unit count");
+        grid = cus;
+    }
+    if ((int64_t)grid > e->nsys) grid = (int)e->nsys;
+    if (nsteps == 0) return RBM_OK;
+    const hipStream_t hs = (hipStream_t)stream;
+
+    // system table and queue order (largest first; ties by index)
+    std::vector<rbm::EnsSys> sys((size_t)e->nsys);
+    std::vector<uint32_t> order((size_t)e->nsys);
+    uint64_t off = 0;
+    for (int64_t i = 0; i < e->nsys; ++i) {
+        rbm::EnsSys &y = sys[(size_t)i];
+        y = rbm::EnsSys{};
+        y.off = (uint32_t)off;
+        y.n = (uint32_t)h_n[i];
+        y.k0 = (uint32_t)(h_seed[i] & 0xffffffffu);
+        y.k1 = (uint32_t)(h_seed[i] >> 32);
+        y.inv_last = (float)(1.0 / (double)(e->p + y.n % (uint32_t)e->p - 1));
+        off += y.n;
+    }
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return sys[a].n > sys[b].n; });
+
+    char *ws = (char *)d_ws;
+    hipError_t he = hipMemcpyAsync(ws + lay.sys, sys.data(), sys.size() * sizeof(rbm::EnsSys), hipMemcpyHostToDevice, hs);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(ws + lay.order, order.data(), order.size() * 4, hipMemcpyHostToDevice, hs);
+    if (he != hipSuccess) return hip_fail(he, "ensemble table upload");
+
+    rbm::EnsLaunch L{};
+    L.base.p = (uint32_t)e->p;
+    L.base.m = (uint32_t)step0;
+    L.base.inv_p1 = (float)(1.0 / (double)(e->p - 1));
+    L.base.a = (float)e->kparam;
+    L.base.beta = (float)e->beta;
+    L.base.dt = (float)e->dt;
+    L.base.ssd = (float)(e->sigma * std::sqrt(e->dt));
+    L.nsteps = nsteps;
+    L.nsys = (uint32_t)e->nsys;
+    L.lds_max = (uint32_t)lds_max;
+    L.grid = (uint32_t)grid;
+    L.sys = ws + lay.sys;
+    L.order = (uint32_t *)(ws + lay.order);
+    L.next = (uint32_t *)(ws + lay.ctl);
+    L.flags = L.next + 1;
+    L.x = d_x;
+    L.state = ws + lay.state;
+    L.stage = ws + lay.stage;
+    L.wst = (uint32_t *)(ws + lay.wst);
+
+    if (!graph) {
+        he = rbm::launch_ensemble(L, e->kernel, hs);
+        if (he != hipSuccess) return hip_fail(he, "ensemble launch");
+    } else {
+        // record the launch on a private stream, replay it once, join the caller's stream
+        hipStream_t cs = nullptr;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&ev1, hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventRecord(ev0, hs);
+        if (he == hipSuccess) he = hipStreamWaitEvent(cs, ev0, 0);
+        if (he == hipSuccess) he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+            hipError_t le = rbm::launch_ensemble(L, e->kernel, cs);
+            he = hipStreamEndCapture(cs, &g);
+            if (le != hipSuccess) he = le;
+        }
+        if (he == hipSuccess) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (he == hipSuccess) he = hipGraphLaunch(ge, cs);
+        if (he == hipSuccess) he = hipEventRecord(ev1, cs);
+        if (he == hipSuccess) he = hipStreamWaitEvent(hs, ev1, 0);
+        if (cs) hipStreamSynchronize(cs);
+        if (ge) hipGraphExecDestroy(ge);
+        if (g) hipGraphDestroy(g);
+        if (ev0) hipEventDestroy(ev0);
+        if (ev1) hipEventDestroy(ev1);
+        if (cs) hipStreamDestroy(cs);
+        if (he != hipSuccess) return hip_fail(he, "ensemble graph");
+    }
+    uint32_t flags = 0;
+    he = hipMemcpyAsync(&flags, L.flags, 4, hipMemcpyDeviceToHost, hs);
+    if (he == hipSuccess) he = hipStreamSynchronize(hs);
+    if (he != hipSuccess) return hip_fail(he, "ensemble completion");
+    if (flags != 0) return fail(RBM_ERR_DEVICE, "a bucket of a streamed system exceeded the LDS capacity");
+    return RBM_OK;
 }
 
 }  // extern "C"

@@ -152,11 +152,13 @@ __device__ __forceinline__ void batch_of(const StepArgs &s, uint32_t r, uint32_t
 // The drift part of the step, x <- x + dt (-beta x + F).  The noise of the
 // same step, sigma sqrt(dt) z(id, m), is added by whichever kernel reads the
 // positions next (deferred noise, below), where the ALU is otherwise idle.
+// The FMAs are written out so that every kernel rounds the update the same
+// way (no contraction left to the compiler).
 template <int D>
 __device__ __forceinline__ void drift_update(const StepArgs &s, float (&x)[D], const float (&f)[D])
 {
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = x[k] + s.dt * (-s.beta * x[k] + f[k]);
+    for (int k = 0; k < D; ++k) x[k] = fmaf(s.dt, fmaf(-s.beta, x[k], f[k]), x[k]);
 }
 
 // Add the noise the stored positions still lack: sigma sqrt(dt) z(id, pm).
@@ -167,7 +169,7 @@ __device__ __forceinline__ void add_pending_noise(const StepArgs &s, float *x, u
         float z[D];
         noise<D>(id, s.pm, s.sys, s.k0, s.k1, z);
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = x[k] + s.pssd * z[k];
+        for (int k = 0; k < D; ++k) x[k] = fmaf(s.pssd, z[k], x[k]);
     }
 }
 
@@ -184,7 +186,7 @@ __device__ __forceinline__ void em_update(const StepArgs &s, float (&x)[D], cons
         for (int k = 0; k < D; ++k) z[k] = 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = x[k] + s.dt * (-s.beta * x[k] + f[k]) + s.ssd * z[k];
+    for (int k = 0; k < D; ++k) x[k] = fmaf(s.ssd, z[k], fmaf(s.dt, fmaf(-s.beta, x[k], f[k]), x[k]));
 }
 
 }  // namespace rbm

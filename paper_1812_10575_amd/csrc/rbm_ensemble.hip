@@ -1,0 +1,471 @@
+// Batched ensemble: many independent RBM-1 systems (Sec. 2.1, Algorithm 1) of
+// uneven size in one persistent launch.
+//
+// Workgroups take systems from an atomic queue ordered by decreasing size
+// (longest first) and run every step of a system before taking the next.
+// System s uses the Philox key seed_s and counter word 3 = s, so each system
+// follows exactly the definitions of a standalone run with those values.
+//
+//   * systems of at most RBM_ENS_LDS particles live in LDS for all steps:
+//     per step the slots draw their PERM words, a counting pass on the top
+//     bits of the word plus an exact rank inside the (tiny) sub-buckets
+//     orders them by key, the batch forces and the Euler-Maruyama update are
+//     applied, and the updated records, in key order, are the next step's
+//     slot order.  HBM is touched only to load and store the system.
+//   * larger systems go through the system's own region of global memory:
+//     a word histogram over ~1024-record buckets, a scatter of the records to
+//     their buckets, then the buckets in order, each sorted in LDS; a batch
+//     cut by the end of a bucket is carried to the next bucket in LDS, so
+//     every batch is complete when it is evaluated.
+#include "rbm_ensemble.hpp"
+#include "rbm_device.hpp"
+
+namespace rbm {
+namespace ens {
+
+constexpr int TPB = 1024;
+constexpr int CAP = RBM_ENS_LDS;          // LDS-resident system size (records)
+constexpr int SB = 12;                    // sub-bucket bits (4096 sub-buckets)
+constexpr int S = 1 << SB;
+constexpr int E = CAP / TPB;              // records per thread
+constexpr int BMEAN = RBM_ENS_BUCKET;     // mean bucket size of the streamed path
+constexpr int MAXB = RBM_ENS_MAXB;        // buckets of the largest streamed system
+
+using Sys = EnsSys;
+
+template <int D>
+struct Lds {
+    Rec<D> a[CAP];     // records (slot order / bucket input)
+    Rec<D> b[CAP];     // records in key order
+    uint32_t w[CAP];   // PERM words
+    uint16_t tmp[CAP]; // sub-bucket member lists
+    uint32_t cnt[S + 1];
+    uint32_t scan[TPB / 64];
+    uint32_t hist[MAXB + 1];
+    uint32_t cur[MAXB];
+    uint32_t sys;
+    uint32_t ncarry;
+};
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan_e(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of a[0..S) (TPB * 4 entries) in place, returns the total
+__device__ uint32_t scan_cnt(uint32_t *a, uint32_t *tmp)
+{
+    const int tid = threadIdx.x;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = a[tid * 4 + k];
+        sum += v[k];
+    }
+    const uint32_t inc = wave_inclusive_scan_e(sum);
+    if ((tid & 63) == 63) tmp[tid >> 6] = inc;
+    __syncthreads();
+    uint32_t off = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w) {
+        const uint32_t t = tmp[w];
+        if (w < (tid >> 6)) off += t;
+        total += t;
+    }
+    uint32_t run = off + inc - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[tid * 4 + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+// Order L.a[0..cnt) by the key (L.w[e] << 32 | L.a[e].id), writing L.b[base +
+// rank].  sub(w) gives the sub-bucket of a word (the bits below the bucket
+// digits).  Ends with a barrier.
+template <int D, typename SubFn>
+__device__ void sort_into_b(Lds<D> &L, uint32_t cnt, uint32_t base, SubFn sub)
+{
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i <= (uint32_t)S; i += TPB) L.cnt[i] = 0;
+    __syncthreads();
+    uint32_t msb[E], mpos[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t e = tid + k * TPB;
+        if (e < cnt) {
+            msb[k] = sub(L.w[e]);
+            mpos[k] = atomicAdd(&L.cnt[msb[k]], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t total = scan_cnt(L.cnt, L.scan);
+    if (tid == 0) L.cnt[S] = total;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t e = tid + k * TPB;
+        if (e < cnt) L.tmp[L.cnt[msb[k]] + mpos[k]] = (uint16_t)e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t e = tid + k * TPB;
+        if (e < cnt) {
+            const uint32_t w = L.w[e], id = L.a[e].id;
+            const uint32_t b0 = L.cnt[msb[k]], b1 = L.cnt[msb[k] + 1];
+            uint32_t rank = b0;
+            for (uint32_t j = b0; j < b1; ++j) {
+                const uint32_t t = L.tmp[j];
+                const uint32_t wt = L.w[t];
+                rank += (wt < w || (wt == w && L.a[t].id < id)) ? 1u : 0u;
+            }
+            L.b[base + rank] = L.a[e];
+        }
+    }
+    __syncthreads();
+}
+
+// The update of the standalone step, in the same FP32 operations: the drift
+// x + dt (-beta x + F), then the noise sigma sqrt(dt) z(id, m).
+template <int D>
+__device__ __forceinline__ void update(const StepArgs &s, float (&x)[D], const float (&f)[D], uint32_t id)
+{
+    drift_update<D>(s, x, f);
+    StepArgs t = s;
+    t.pm = s.m;
+    t.pssd = s.ssd;
+    add_pending_noise<D>(t, x, id);
+}
+
+// Forces and update of the batches of ranks [r0, r1) held in key order at
+// src[0..): batches start at multiples of p (r0 is one); the batch of the
+// last rank of a system (r1 == n) takes the leftover ranks.  Writes the
+// updated record of rank r to out(r).
+template <int D, int KERN, int P, typename Out>
+__device__ void batches(const StepArgs &s, const Rec<D> *src, uint32_t r0, uint32_t r1, Out out)
+{
+    const uint32_t p = s.p;
+    const uint32_t nq = (r1 - r0) / p;  // the last batch may be longer than p
+    for (uint32_t qq = threadIdx.x; qq < nq; qq += TPB) {
+        const uint32_t bs = r0 + qq * p;
+        const bool last = (qq == nq - 1) && (r1 == s.n);
+        const uint32_t sz = last ? r1 - bs : p;
+        const Rec<D> *b = src + (bs - r0);
+        if (P > 0 && sz == (uint32_t)P) {
+            float x[P > 0 ? P : 1][D], f[P > 0 ? P : 1][D];
+            uint32_t id[P > 0 ? P : 1];
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const Rec<D> r = b[i];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    x[i][c] = r.x[c];
+                    f[i][c] = 0.0f;
+                }
+                id[i] = r.id;
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+                for (int j = i + 1; j < P; ++j) {
+                    float dx[D], r2 = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        dx[c] = x[i][c] - x[j][c];
+                        r2 = fmaf(dx[c], dx[c], r2);
+                    }
+                    const float sc = pair_scale<KERN>(r2, s.a);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        f[i][c] = fmaf(sc, dx[c], f[i][c]);
+                        f[j][c] = fmaf(-sc, dx[c], f[j][c]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) f[i][c] *= s.inv_p1;
+                update<D>(s, x[i], f[i], id[i]);
+                Rec<D> o;
+#pragma unroll
+                for (int c = 0; c < D; ++c) o.x[c] = x[i][c];
+                o.id = id[i];
+                out(bs + i, o);
+            }
+        } else {
+            const float inv = (sz == p) ? s.inv_p1 : s.inv_last;
+            for (uint32_t i = 0; i < sz; ++i) {
+                const Rec<D> me = b[i];
+                float xi[D], f[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    xi[c] = me.x[c];
+                    f[c] = 0.0f;
+                }
+                for (uint32_t j = 0; j < sz; ++j)
+                    if (j != i) add_pair<D, KERN>(xi, b[j].x, s.a, f);
+#pragma unroll
+                for (int c = 0; c < D; ++c) f[c] *= inv;
+                update<D>(s, xi, f, me.id);
+                Rec<D> o;
+#pragma unroll
+                for (int c = 0; c < D; ++c) o.x[c] = xi[c];
+                o.id = me.id;
+                out(bs + i, o);
+            }
+        }
+    }
+}
+
+// PERM words of 4 consecutive slots k..k+3
+__device__ __forceinline__ uint4 words4(const StepArgs &s, uint32_t k)
+{
+    return philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
+}
+
+template <int D, int KERN, int P>
+__device__ void run_small(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restrict__ x)
+{
+    const uint32_t n = s.n, tid = threadIdx.x;
+    for (uint32_t k = tid; k < n; k += TPB) {
+        Rec<D> r;
+#pragma unroll
+        for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)k * D + c];
+        r.id = k;
+        L.a[k] = r;
+    }
+    __syncthreads();
+    const uint32_t m0 = s.m;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        s.m = m0 + (uint32_t)t;
+        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+            const uint4 w = words4(s, k);
+            L.w[k] = w.x;
+            if (k + 1 < n) L.w[k + 1] = w.y;
+            if (k + 2 < n) L.w[k + 2] = w.z;
+            if (k + 3 < n) L.w[k + 3] = w.w;
+        }
+        __syncthreads();
+        sort_into_b<D>(L, n, 0, [](uint32_t w) { return w >> (32 - SB); });
+        // b (key order, old positions) -> a (key order, new positions)
+        batches<D, KERN, P>(s, L.b, 0, n, [&](uint32_t r, const Rec<D> &o) { L.a[r] = o; });
+        __syncthreads();
+    }
+    for (uint32_t k = tid; k < n; k += TPB) {
+        const Rec<D> r = L.a[k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[(size_t)r.id * D + c] = r.x[c];
+    }
+}
+
+template <int D, int KERN, int P>
+__device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restrict__ x,
+                          Rec<D> *__restrict__ state, Rec<D> *__restrict__ stage,
+                          uint32_t *__restrict__ wst, uint32_t *__restrict__ flags)
+{
+    const uint32_t n = s.n, tid = threadIdx.x;
+    const uint32_t nbk = (n + BMEAN - 1) / BMEAN;  // <= MAXB by the host's checks
+    for (uint32_t k = tid; k < n; k += TPB) {
+        Rec<D> r;
+#pragma unroll
+        for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)k * D + c];
+        r.id = k;
+        state[k] = r;
+    }
+    __threadfence();
+    __syncthreads();
+    const uint32_t m0 = s.m;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        s.m = m0 + (uint32_t)t;
+        // 1. bucket histogram of the words (no memory read)
+        for (uint32_t i = tid; i <= nbk; i += TPB) L.hist[i] = 0;
+        __syncthreads();
+        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+            const uint4 w = words4(s, k);
+            atomicAdd(&L.hist[__umulhi(w.x, nbk)], 1u);
+            if (k + 1 < n) atomicAdd(&L.hist[__umulhi(w.y, nbk)], 1u);
+            if (k + 2 < n) atomicAdd(&L.hist[__umulhi(w.z, nbk)], 1u);
+            if (k + 3 < n) atomicAdd(&L.hist[__umulhi(w.w, nbk)], 1u);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // exclusive scan of nbk <= 256 counts by one wavefront
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = tid * 4 + k;
+                v[k] = i < nbk ? L.hist[i] : 0u;
+                sum += v[k];
+            }
+            const uint32_t inc = wave_inclusive_scan_e(sum);
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = tid * 4 + k;
+                if (i < nbk) {
+                    L.hist[i] = run;
+                    L.cur[i] = run;
+                }
+                run += v[k];
+            }
+            if (tid == 0) L.hist[nbk] = n;
+        }
+        __syncthreads();
+        // 2. records to their buckets (order inside a bucket is free)
+        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+            const uint4 w = words4(s, k);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                if (k + j < n) {
+                    const uint32_t wj = word_of(w, j);
+                    const uint32_t pos = atomicAdd(&L.cur[__umulhi(wj, nbk)], 1u);
+                    stage[pos] = state[k + j];
+                    wst[pos] = wj;
+                }
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        // 3. buckets in order; the batch cut by a bucket's end is carried
+        if (tid == 0) L.ncarry = 0;
+        __syncthreads();
+        for (uint32_t bk = 0; bk < nbk; ++bk) {
+            const uint32_t lo = L.hist[bk], hi = L.hist[bk + 1], cnt = hi - lo;
+            const uint32_t nc = L.ncarry;
+            if (nc + cnt > (uint32_t)CAP) {  // far beyond any bucket's spread: flag, give up the step
+                if (tid == 0) atomicOr(flags, 1u);
+                break;
+            }
+            for (uint32_t e = tid; e < cnt; e += TPB) {
+                L.a[e] = stage[lo + e];
+                L.w[e] = wst[lo + e];
+            }
+            __syncthreads();
+            sort_into_b<D>(L, cnt, nc, [nbk](uint32_t w) { return (w * nbk) >> (32 - SB); });
+            // L.b[0..nc) carried records (ranks lo - nc ..), then this bucket
+            const uint32_t r0 = lo - nc;
+            uint32_t r1;  // end of the complete batches
+            if (hi == n) {
+                r1 = n;
+            } else {
+                r1 = r0 + ((hi - r0) / s.p) * s.p;
+                // the last batch of the system starts at (nbat - 1) p and runs to n
+                const uint32_t last_start = (s.nbat - 1) * s.p;
+                if (r1 > last_start) r1 = last_start > r0 ? last_start : r0;
+            }
+            batches<D, KERN, P>(s, L.b, r0, r1 > r0 ? r1 : r0,
+                                [&](uint32_t r, const Rec<D> &o) { state[r] = o; });
+            __syncthreads();
+            const uint32_t keep = hi - (r1 > r0 ? r1 : r0);
+            const uint32_t from = (r1 > r0 ? r1 : r0) - r0;
+            Rec<D> mv[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const uint32_t e = tid + k * TPB;
+                if (e < keep) mv[k] = L.b[from + e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const uint32_t e = tid + k * TPB;
+                if (e < keep) L.b[e] = mv[k];
+            }
+            if (tid == 0) L.ncarry = keep;
+            __syncthreads();
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    for (uint32_t k = tid; k < n; k += TPB) {
+        const Rec<D> r = state[k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[(size_t)r.id * D + c] = r.x[c];
+    }
+}
+
+template <int D, int KERN, int P>
+__global__ __launch_bounds__(TPB) void k_ensemble(StepArgs base, int64_t nsteps, uint32_t nsys,
+                                                  uint32_t lds_max, const Sys *__restrict__ sys,
+                                                  const uint32_t *__restrict__ order,
+                                                  uint32_t *__restrict__ next,
+                                                  float *__restrict__ x, Rec<D> *__restrict__ state,
+                                                  Rec<D> *__restrict__ stage,
+                                                  uint32_t *__restrict__ wst,
+                                                  uint32_t *__restrict__ flags)
+{
+    __shared__ Lds<D> L;
+    for (;;) {
+        if (threadIdx.x == 0) L.sys = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t q = L.sys;
+        __syncthreads();
+        if (q >= nsys) break;  // every workgroup leaves once the queue is empty
+        const uint32_t id = order[q];
+        const Sys sy = sys[id];
+        StepArgs s = base;
+        s.n = sy.n;
+        s.nbat = sy.n / s.p;
+        s.inv_last = sy.inv_last;
+        s.k0 = sy.k0;
+        s.k1 = sy.k1;
+        s.sys = id;
+        float *xs = x + (size_t)sy.off * D;
+        if (sy.n <= lds_max)
+            run_small<D, KERN, P>(L, s, nsteps, xs);
+        else
+            run_large<D, KERN, P>(L, s, nsteps, xs, state + sy.off, stage + sy.off, wst + sy.off, flags);
+        __syncthreads();
+    }
+}
+
+// queue counter and error flags to zero (a kernel, so that the launch can be
+// recorded into a graph)
+__global__ void k_zero(uint32_t *p)
+{
+    if (threadIdx.x < 2) p[threadIdx.x] = 0u;
+}
+
+}  // namespace ens
+
+namespace {
+
+template <int D, int KERN>
+hipError_t ens_dk(const EnsLaunch &e, hipStream_t st)
+{
+#define RBM_ENS(PP)                                                                             \
+    hipLaunchKernelGGL((ens::k_ensemble<D, KERN, PP>), dim3(e.grid), dim3(ens::TPB), 0, st,      \
+                       e.base, e.nsteps, e.nsys, e.lds_max, (const ens::Sys *)e.sys, e.order,     \
+                       e.next, e.x, (Rec<D> *)e.state, (Rec<D> *)e.stage, e.wst, e.flags)
+    switch (e.base.p) {
+    case 2: RBM_ENS(2); break;
+    case 4: RBM_ENS(4); break;
+    case 8: RBM_ENS(8); break;
+    default: RBM_ENS(0); break;
+    }
+#undef RBM_ENS
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ensemble(const EnsLaunch &e, int kernel, hipStream_t st)
+{
+    hipLaunchKernelGGL(ens::k_zero, dim3(1), dim3(64), 0, st, e.next);
+    switch (kernel) {
+    case K_GAUSS: return ens_dk<2, K_GAUSS>(e, st);
+    case K_SOFTCOULOMB: return ens_dk<2, K_SOFTCOULOMB>(e, st);
+    default: return ens_dk<2, K_ATTREP>(e, st);
+    }
+}
+
+
+}  // namespace rbm

@@ -1,0 +1,42 @@
+// Batched ensemble of independent RBM-1 systems: launch parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rbm_device.hpp"
+
+#define RBM_ENS_LDS 4096     // largest system kept in LDS for all steps (d = 2)
+#define RBM_ENS_BUCKET 1024  // mean bucket of a streamed system
+#define RBM_ENS_MAXB 256     // buckets of the largest streamed system
+#define RBM_ENS_MAXN (RBM_ENS_MAXB * RBM_ENS_BUCKET)
+
+namespace rbm {
+
+struct EnsSys {
+    uint32_t off;     // first particle of the system in the packed arrays
+    uint32_t n;       // particles
+    uint32_t k0, k1;  // Philox key (seed)
+    float inv_last;   // 1 / (s - 1) of the last batch, s = p + n mod p
+    uint32_t pad[3];
+};
+
+struct EnsLaunch {
+    StepArgs base;      // shared model parameters; step index in base.m
+    int64_t nsteps;
+    uint32_t nsys;
+    uint32_t lds_max;   // systems up to this size stay in LDS
+    uint32_t grid;      // persistent workgroups
+    void *sys;          // per-system table (offset, n, key)
+    uint32_t *order;    // queue order (largest first)
+    uint32_t *next;     // queue counter; next[1]: error flags
+    float *x;           // packed positions, by (system, id), in and out
+    void *state, *stage;
+    uint32_t *wst;
+    uint32_t *flags;    // == next + 1
+};
+
+hipError_t launch_ensemble(const EnsLaunch &e, int kernel, hipStream_t st);
+
+}  // namespace rbm

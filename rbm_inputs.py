@@ -80,6 +80,21 @@ WORKLOADS = {
 }
 
 
+# Ensemble of independent 2-D Gaussian systems (the first workload's kernel,
+# trap, noise and step), sizes log-uniform on [64, 65536], Philox key of
+# system s = 1 + s, initial positions standard normal.
+ENSEMBLE = dict(name="gauss2d-ensemble-4096", d=2, kernel=0, p=4, kparam=0.0, beta=1.0, sigma=0.5,
+                dt=1e-3, nsys=4096, nmin=64, nmax=65536, steps=500, seed=5)
+
+
+def ensemble(nsys: int = ENSEMBLE["nsys"], nmin: int = ENSEMBLE["nmin"], nmax: int = ENSEMBLE["nmax"],
+             seed: int = ENSEMBLE["seed"]):
+    """(sizes int64 [nsys], keys uint64 [nsys], x0 float32 [sum sizes][2])."""
+    n = ensemble_sizes(nsys, nmin, nmax, seed)
+    keys = 1 + np.arange(nsys, dtype=np.uint64)
+    return n, keys, normal(int(n.sum()), 2, seed + 1)
+
+
 def params_of(name: str, **over) -> dict:
     """Parameter dict of a named workload, with overrides."""
     w = dict(WORKLOADS[name])
