@@ -125,6 +125,39 @@ def force_mse(args) -> dict:
     return out
 
 
+def ensemble_rate(args) -> dict:
+    """The batched ensemble: 4096 independent 2-D Gaussian systems, N_s
+    log-uniform on [64, 65536], p = 4, 500 steps in one persistent launch
+    recorded into a hipGraph, with the tile from the autotuner."""
+    import numpy as np
+    import torch
+    import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import autotune
+    import rbm_inputs
+    E = rbm_inputs.ENSEMBLE
+    n, keys, x0 = rbm_inputs.ensemble()
+    ens = rbm.Ensemble(d=E["d"], kernel=E["kernel"], p=E["p"], sizes=n, seeds=keys, kparam=E["kparam"],
+                       beta=E["beta"], sigma=E["sigma"], dt=E["dt"])
+    x = torch.from_numpy(x0).cuda()
+    t0 = time.perf_counter()
+    tile = autotune.tune(ens, x, retune=args.retune)
+    t_tune = time.perf_counter() - t0
+    ws = torch.empty(rbm.ensemble_workspace_size(ens), dtype=torch.uint8, device=x.device)
+    xr = x.clone()
+    rbm.ensemble_run(ens, xr, 0, 5, ws=ws, graph=True, **tile)  # warm-up
+    xr.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbm.ensemble_run(ens, xr, 0, E["steps"], ws=ws, graph=True, **tile)
+    dt = time.perf_counter() - t0
+    assert bool(torch.isfinite(xr).all())
+    tot = int(n.sum())
+    return {"workload": E["name"], "systems": int(len(n)), "particles": tot, "steps": E["steps"], "p": E["p"],
+            "seconds": round(dt, 4), "value": tot * E["steps"] / dt, "unit": "particle-steps/s",
+            "tile": tile, "tune_seconds": round(t_tune, 2),
+            "launch": "one persistent kernel replayed from a hipGraph; wall clock around the call"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +171,8 @@ def main() -> int:
     ap.add_argument("--train-batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--mse-snap-every", type=int, default=25)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble part")
+    ap.add_argument("--retune", action="store_true", help="ignore the ensemble autotune cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -216,6 +251,8 @@ def main() -> int:
     }
     if not args.no_mse:
         out["force_mse"] = force_mse(args)
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_rate(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

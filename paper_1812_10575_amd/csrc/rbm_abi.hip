@@ -579,7 +579,7 @@ static_assert(RBM_ENS_LDS == 4096 && RBM_ENS_MAXN == 256 * 1024, "ensemble limit
 namespace {
 
 struct EnsLayout {
-    size_t sys, order, ctl, state, stage, wst, total;
+    size_t sys, order, items, ctl, state, stage, wst, total;
     uint64_t nsum;
 };
 
@@ -612,6 +612,7 @@ rbm_status ens_check(const rbm_ensemble *e, const int64_t *h_n, EnsLayout *lay)
     lay->nsum = nsum;
     lay->sys = take((size_t)e->nsys * sizeof(rbm::EnsSys));
     lay->order = take((size_t)e->nsys * 4);
+    lay->items = take((size_t)e->nsys * 8);
     lay->ctl = take(8);
     lay->state = take(nsum * sizeof(rbm::Rec<2>));
     lay->stage = take(nsum * sizeof(rbm::Rec<2>));
@@ -650,9 +651,21 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     if (graph != 0 && graph != 1) return fail(RBM_ERR_INVALID, "graph must be 0 or 1");
     int lds_max = tile ? tile->lds_max : 0;
     int grid = tile ? tile->grid : 0;
+    int team = tile ? tile->team : 0;
+    int bucket = tile ? tile->bucket : 0;
     if (lds_max == 0) lds_max = RBM_ENS_LDS;
+    if (team == 0) team = 256;
+    if (bucket == 0) bucket = 2048;
     if (lds_max < 0 || lds_max > RBM_ENS_LDS) return fail(RBM_ERR_INVALID, "lds_max = %d not in 0..%d", lds_max, RBM_ENS_LDS);
     if (grid < 0 || grid > 65536) return fail(RBM_ERR_INVALID, "grid = %d not in 0..65536", grid);
+    if (team < 64 || team > 1024 || (team & (team - 1)) != 0)
+        return fail(RBM_ERR_INVALID, "team = %d is not a power of two in 64..1024", team);
+    if (bucket < 256 || bucket > 3072) return fail(RBM_ERR_INVALID, "bucket = %d not in 256..3072", bucket);
+    int64_t nmax = 0;
+    for (int64_t i = 0; i < e->nsys; ++i) nmax = std::max(nmax, h_n[i]);
+    if (nmax > lds_max && (nmax + bucket - 1) / bucket > RBM_ENS_MAXB)
+        return fail(RBM_ERR_INVALID, "bucket = %d gives more than %d buckets for N = %lld", bucket, RBM_ENS_MAXB,
+                    (long long)nmax);
     if (grid == 0) {
         int dev = 0, cus = 0;
         hipError_t he = hipGetDevice(&dev);
@@ -660,7 +673,6 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
         if (he != hipSuccess) return hip_fail(he, "compute unit count");
         grid = cus;
     }
-    if ((int64_t)grid > e->nsys) grid = (int)e->nsys;
     if (nsteps == 0) return RBM_OK;
     const hipStream_t hs = (hipStream_t)stream;
 
@@ -680,11 +692,26 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     }
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return sys[a].n > sys[b].n; });
+    // work items in queue order: every system above 4 team particles alone,
+    // then the rest in groups of 1024 / team consecutive systems
+    std::vector<uint32_t> items;  // pairs (first, count)
+    const uint32_t g = 1024u / (uint32_t)team, cap = 4u * (uint32_t)team;
+    for (size_t i = 0; i < order.size();) {
+        uint32_t c = 1;
+        if (g > 1 && sys[order[i]].n <= cap) c = (uint32_t)std::min<size_t>(g, order.size() - i);
+        items.push_back((uint32_t)i);
+        items.push_back(c);
+        i += c;
+    }
+    const uint32_t nitems = (uint32_t)(items.size() / 2);
+    if ((int64_t)grid > nitems) grid = (int)nitems;
 
     char *ws = (char *)d_ws;
     hipError_t he = hipMemcpyAsync(ws + lay.sys, sys.data(), sys.size() * sizeof(rbm::EnsSys), hipMemcpyHostToDevice, hs);
     if (he == hipSuccess)
         he = hipMemcpyAsync(ws + lay.order, order.data(), order.size() * 4, hipMemcpyHostToDevice, hs);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(ws + lay.items, items.data(), items.size() * 4, hipMemcpyHostToDevice, hs);
     if (he != hipSuccess) return hip_fail(he, "ensemble table upload");
 
     rbm::EnsLaunch L{};
@@ -696,11 +723,14 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     L.base.dt = (float)e->dt;
     L.base.ssd = (float)(e->sigma * std::sqrt(e->dt));
     L.nsteps = nsteps;
-    L.nsys = (uint32_t)e->nsys;
+    L.nitems = nitems;
     L.lds_max = (uint32_t)lds_max;
+    L.team = (uint32_t)team;
+    L.bmean = (uint32_t)bucket;
     L.grid = (uint32_t)grid;
     L.sys = ws + lay.sys;
-    L.order = (uint32_t *)(ws + lay.order);
+    L.order = (const uint32_t *)(ws + lay.order);
+    L.items = (const uint2 *)(ws + lay.items);
     L.next = (uint32_t *)(ws + lay.ctl);
     L.flags = L.next + 1;
     L.x = d_x;

@@ -1,22 +1,29 @@
 // Batched ensemble: many independent RBM-1 systems (Sec. 2.1, Algorithm 1) of
 // uneven size in one persistent launch.
 //
-// Workgroups take systems from an atomic queue ordered by decreasing size
-// (longest first) and run every step of a system before taking the next.
 // System s uses the Philox key seed_s and counter word 3 = s, so each system
 // follows exactly the definitions of a standalone run with those values.
+// Workgroups take work items from an atomic queue that the host orders by
+// decreasing cost (longest first) and run every step of an item before
+// taking the next.  An item is either one system, run by the whole
+// workgroup, or a group of up to TPB / T small systems, run side by side by
+// teams of T threads (each team with its own slice of the LDS arrays; the
+// workgroup barriers keep the teams in step).
 //
-//   * systems of at most RBM_ENS_LDS particles live in LDS for all steps:
-//     per step the slots draw their PERM words, a counting pass on the top
-//     bits of the word plus an exact rank inside the (tiny) sub-buckets
-//     orders them by key, the batch forces and the Euler-Maruyama update are
-//     applied, and the updated records, in key order, are the next step's
-//     slot order.  HBM is touched only to load and store the system.
-//   * larger systems go through the system's own region of global memory:
-//     a word histogram over ~1024-record buckets, a scatter of the records to
-//     their buckets, then the buckets in order, each sorted in LDS; a batch
-//     cut by the end of a bucket is carried to the next bucket in LDS, so
-//     every batch is complete when it is evaluated.
+//   * a system of at most 4 T particles (4 TPB for a whole-workgroup item up
+//     to lds_max) lives in LDS for all steps: per step the slots draw their
+//     PERM words, a counting pass on the top bits of the word plus an exact
+//     rank inside the (tiny) sub-buckets orders them by key, the batch forces
+//     and the Euler-Maruyama update are applied, and the updated records, in
+//     key order, are the next step's slot order.  HBM is touched only to load
+//     and store the system.
+//   * a larger system goes through its own region of global memory (written
+//     and read by one workgroup only, so the workgroup barrier orders it; a
+//     device-scope fence would write back and invalidate the L2 of the whole
+//     XCD): a word histogram over buckets of about bmean records, a scatter
+//     of the records to their buckets, then the buckets in order, each sorted
+//     in LDS; a batch cut by the end of a bucket is carried to the next
+//     bucket in LDS, so every batch is complete when it is evaluated.
 #include "rbm_ensemble.hpp"
 #include "rbm_device.hpp"
 
@@ -24,28 +31,49 @@ namespace rbm {
 namespace ens {
 
 constexpr int TPB = 1024;
-constexpr int CAP = RBM_ENS_LDS;          // LDS-resident system size (records)
-constexpr int SB = 12;                    // sub-bucket bits (4096 sub-buckets)
-constexpr int S = 1 << SB;
-constexpr int E = CAP / TPB;              // records per thread
-constexpr int BMEAN = RBM_ENS_BUCKET;     // mean bucket size of the streamed path
-constexpr int MAXB = RBM_ENS_MAXB;        // buckets of the largest streamed system
+constexpr int CAP = RBM_ENS_LDS;  // records in LDS (all teams together)
+constexpr int S = CAP;            // sub-bucket counters (4 per thread)
+constexpr int E = CAP / TPB;      // records per thread
+constexpr int MAXB = RBM_ENS_MAXB;
+constexpr int MAXG = TPB / 64;    // teams per workgroup at most
 
 using Sys = EnsSys;
 
 template <int D>
 struct Lds {
-    Rec<D> a[CAP];     // records (slot order / bucket input)
-    Rec<D> b[CAP];     // records in key order
-    uint32_t w[CAP];   // PERM words
-    uint16_t tmp[CAP]; // sub-bucket member lists
-    uint32_t cnt[S + 1];
+    Rec<D> a[CAP];      // records (slot order / bucket input)
+    Rec<D> b[CAP];      // records in key order
+    uint32_t w[CAP];    // PERM words
+    uint16_t tmp[CAP];  // sub-bucket member lists
+    uint32_t cnt[S];    // sub-bucket counts, then starts (team slices of 4 T)
+    uint32_t tot[MAXG]; // records per team slice
     uint32_t scan[TPB / 64];
     uint32_t hist[MAXB + 1];
     uint32_t cur[MAXB];
-    uint32_t sys;
+    uint32_t item;
     uint32_t ncarry;
 };
+
+// A team: threads [tb T, (tb + 1) T) of the workgroup, owning records
+// [tb 4T, (tb + 1) 4T) and counters [tb 4T, (tb + 1) 4T).
+struct Team {
+    uint32_t T;     // threads (a power of two, 64 .. TPB)
+    uint32_t lg;    // log2(4 T): sub-bucket bits
+    uint32_t tb;    // team index
+    uint32_t lt;    // thread index in the team
+    uint32_t base;  // first record / counter of the team
+};
+
+__device__ __forceinline__ Team make_team(uint32_t T)
+{
+    Team t;
+    t.T = T;
+    t.lg = 33u - __clz(T);  // log2(T) + 2
+    t.tb = threadIdx.x / T;
+    t.lt = threadIdx.x % T;
+    t.base = t.tb * 4u * T;
+    return t;
+}
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan_e(uint32_t v)
 {
@@ -58,77 +86,80 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan_e(uint32_t v)
     return v;
 }
 
-// exclusive scan of a[0..S) (TPB * 4 entries) in place, returns the total
-__device__ uint32_t scan_cnt(uint32_t *a, uint32_t *tmp)
+// Exclusive scan of every team's counter slice in place (thread tid owns
+// counters 4 tid .. 4 tid + 3, which lie in its team's slice); the team's
+// total goes to L.tot.  Ends with a barrier.
+template <int D>
+__device__ void scan_cnt(Lds<D> &L, const Team &tm)
 {
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     uint32_t v[4], sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        v[k] = a[tid * 4 + k];
+        v[k] = L.cnt[tid * 4 + k];
         sum += v[k];
     }
     const uint32_t inc = wave_inclusive_scan_e(sum);
-    if ((tid & 63) == 63) tmp[tid >> 6] = inc;
+    if ((tid & 63) == 63) L.scan[tid >> 6] = inc;
     __syncthreads();
+    const uint32_t w0 = tm.tb * (tm.T >> 6), w1 = w0 + (tm.T >> 6), me = tid >> 6;
     uint32_t off = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < TPB / 64; ++w) {
-        const uint32_t t = tmp[w];
-        if (w < (tid >> 6)) off += t;
+    for (uint32_t w = w0; w < w1; ++w) {
+        const uint32_t t = L.scan[w];
+        if (w < me) off += t;
         total += t;
     }
     uint32_t run = off + inc - sum;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        a[tid * 4 + k] = run;
+        L.cnt[tid * 4 + k] = run;
         run += v[k];
     }
+    if (tm.lt == 0) L.tot[tm.tb] = total;
     __syncthreads();
-    return total;
 }
 
-// Order L.a[0..cnt) by the key (L.w[e] << 32 | L.a[e].id), writing L.b[base +
-// rank].  sub(w) gives the sub-bucket of a word (the bits below the bucket
-// digits).  Ends with a barrier.
+// Order the team's records a[0..cnt) (team-relative) by the key
+// (w << 32 | id), writing b[base_b + rank].  sub(w) is the sub-bucket of a
+// word, monotone in w, in [0, 4 T).  Ends with a barrier.
 template <int D, typename SubFn>
-__device__ void sort_into_b(Lds<D> &L, uint32_t cnt, uint32_t base, SubFn sub)
+__device__ void sort_into_b(Lds<D> &L, const Team &tm, uint32_t cnt, uint32_t base_b, SubFn sub)
 {
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i <= (uint32_t)S; i += TPB) L.cnt[i] = 0;
+    const uint32_t tid = threadIdx.x, R = tm.base;
+    for (uint32_t i = tid; i < (uint32_t)S; i += TPB) L.cnt[i] = 0;
     __syncthreads();
     uint32_t msb[E], mpos[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const uint32_t e = tid + k * TPB;
+        const uint32_t e = tm.lt + k * tm.T;
         if (e < cnt) {
-            msb[k] = sub(L.w[e]);
-            mpos[k] = atomicAdd(&L.cnt[msb[k]], 1u);
+            msb[k] = sub(L.w[R + e]);
+            mpos[k] = atomicAdd(&L.cnt[R + msb[k]], 1u);
         }
     }
     __syncthreads();
-    const uint32_t total = scan_cnt(L.cnt, L.scan);
-    if (tid == 0) L.cnt[S] = total;
-    __syncthreads();
+    scan_cnt<D>(L, tm);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const uint32_t e = tid + k * TPB;
-        if (e < cnt) L.tmp[L.cnt[msb[k]] + mpos[k]] = (uint16_t)e;
+        const uint32_t e = tm.lt + k * tm.T;
+        if (e < cnt) L.tmp[R + L.cnt[R + msb[k]] + mpos[k]] = (uint16_t)e;
     }
     __syncthreads();
+    const uint32_t top = 4u * tm.T - 1u;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const uint32_t e = tid + k * TPB;
+        const uint32_t e = tm.lt + k * tm.T;
         if (e < cnt) {
-            const uint32_t w = L.w[e], id = L.a[e].id;
-            const uint32_t b0 = L.cnt[msb[k]], b1 = L.cnt[msb[k] + 1];
+            const uint32_t w = L.w[R + e], id = L.a[R + e].id;
+            const uint32_t b0 = L.cnt[R + msb[k]];
+            const uint32_t b1 = msb[k] < top ? L.cnt[R + msb[k] + 1] : L.tot[tm.tb];
             uint32_t rank = b0;
             for (uint32_t j = b0; j < b1; ++j) {
-                const uint32_t t = L.tmp[j];
-                const uint32_t wt = L.w[t];
-                rank += (wt < w || (wt == w && L.a[t].id < id)) ? 1u : 0u;
+                const uint32_t t = L.tmp[R + j];
+                const uint32_t wt = L.w[R + t];
+                rank += (wt < w || (wt == w && L.a[R + t].id < id)) ? 1u : 0u;
             }
-            L.b[base + rank] = L.a[e];
+            L.b[R + base_b + rank] = L.a[R + e];
         }
     }
     __syncthreads();
@@ -149,13 +180,14 @@ __device__ __forceinline__ void update(const StepArgs &s, float (&x)[D], const f
 // Forces and update of the batches of ranks [r0, r1) held in key order at
 // src[0..): batches start at multiples of p (r0 is one); the batch of the
 // last rank of a system (r1 == n) takes the leftover ranks.  Writes the
-// updated record of rank r to out(r).
+// updated record of rank r to out(r).  The team's threads share the batches.
 template <int D, int KERN, int P, typename Out>
-__device__ void batches(const StepArgs &s, const Rec<D> *src, uint32_t r0, uint32_t r1, Out out)
+__device__ void batches(const StepArgs &s, const Team &tm, const Rec<D> *src, uint32_t r0, uint32_t r1,
+                        Out out)
 {
     const uint32_t p = s.p;
     const uint32_t nq = (r1 - r0) / p;  // the last batch may be longer than p
-    for (uint32_t qq = threadIdx.x; qq < nq; qq += TPB) {
+    for (uint32_t qq = tm.lt; qq < nq; qq += tm.T) {
         const uint32_t bs = r0 + qq * p;
         const bool last = (qq == nq - 1) && (r1 == s.n);
         const uint32_t sz = last ? r1 - bs : p;
@@ -232,48 +264,53 @@ __device__ __forceinline__ uint4 words4(const StepArgs &s, uint32_t k)
     return philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
 }
 
+// The team's system (n <= 4 T particles, n = 0 for an idle team) in LDS for
+// all steps.  Every team of the workgroup runs the same number of steps.
 template <int D, int KERN, int P>
-__device__ void run_small(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restrict__ x)
+__device__ void run_small(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps, float *__restrict__ x)
 {
-    const uint32_t n = s.n, tid = threadIdx.x;
-    for (uint32_t k = tid; k < n; k += TPB) {
+    const uint32_t n = s.n, R = tm.base;
+    for (uint32_t k = tm.lt; k < n; k += tm.T) {
         Rec<D> r;
 #pragma unroll
         for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)k * D + c];
         r.id = k;
-        L.a[k] = r;
+        L.a[R + k] = r;
     }
     __syncthreads();
-    const uint32_t m0 = s.m;
+    const uint32_t m0 = s.m, sh = 32u - tm.lg;
     for (int64_t t = 0; t < nsteps; ++t) {
         s.m = m0 + (uint32_t)t;
-        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+        for (uint32_t k = 4 * tm.lt; k < n; k += 4 * tm.T) {
             const uint4 w = words4(s, k);
-            L.w[k] = w.x;
-            if (k + 1 < n) L.w[k + 1] = w.y;
-            if (k + 2 < n) L.w[k + 2] = w.z;
-            if (k + 3 < n) L.w[k + 3] = w.w;
+            L.w[R + k] = w.x;
+            if (k + 1 < n) L.w[R + k + 1] = w.y;
+            if (k + 2 < n) L.w[R + k + 2] = w.z;
+            if (k + 3 < n) L.w[R + k + 3] = w.w;
         }
         __syncthreads();
-        sort_into_b<D>(L, n, 0, [](uint32_t w) { return w >> (32 - SB); });
+        sort_into_b<D>(L, tm, n, 0, [sh](uint32_t w) { return w >> sh; });
         // b (key order, old positions) -> a (key order, new positions)
-        batches<D, KERN, P>(s, L.b, 0, n, [&](uint32_t r, const Rec<D> &o) { L.a[r] = o; });
+        if (n > 0)
+            batches<D, KERN, P>(s, tm, L.b + R, 0, n, [&](uint32_t r, const Rec<D> &o) { L.a[R + r] = o; });
         __syncthreads();
     }
-    for (uint32_t k = tid; k < n; k += TPB) {
-        const Rec<D> r = L.a[k];
+    for (uint32_t k = tm.lt; k < n; k += tm.T) {
+        const Rec<D> r = L.a[R + k];
 #pragma unroll
         for (int c = 0; c < D; ++c) x[(size_t)r.id * D + c] = r.x[c];
     }
 }
 
+// One system streamed through global memory by the whole workgroup (tm is
+// the workgroup as one team).
 template <int D, int KERN, int P>
-__device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restrict__ x,
-                          Rec<D> *__restrict__ state, Rec<D> *__restrict__ stage,
+__device__ void run_large(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps, uint32_t bmean,
+                          float *__restrict__ x, Rec<D> *__restrict__ state, Rec<D> *__restrict__ stage,
                           uint32_t *__restrict__ wst, uint32_t *__restrict__ flags)
 {
     const uint32_t n = s.n, tid = threadIdx.x;
-    const uint32_t nbk = (n + BMEAN - 1) / BMEAN;  // <= MAXB by the host's checks
+    const uint32_t nbk = (n + bmean - 1) / bmean;  // <= MAXB by the host's checks
     for (uint32_t k = tid; k < n; k += TPB) {
         Rec<D> r;
 #pragma unroll
@@ -281,7 +318,6 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
         r.id = k;
         state[k] = r;
     }
-    __threadfence();
     __syncthreads();
     const uint32_t m0 = s.m;
     for (int64_t t = 0; t < nsteps; ++t) {
@@ -333,7 +369,6 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
                 }
             }
         }
-        __threadfence();
         __syncthreads();
         // 3. buckets in order; the batch cut by a bucket's end is carried
         if (tid == 0) L.ncarry = 0;
@@ -350,7 +385,8 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
                 L.w[e] = wst[lo + e];
             }
             __syncthreads();
-            sort_into_b<D>(L, cnt, nc, [nbk](uint32_t w) { return (w * nbk) >> (32 - SB); });
+            // sub-bucket: the next 12 bits of w nbk / 2^32 below the bucket
+            sort_into_b<D>(L, tm, cnt, nc, [nbk](uint32_t w) { return (w * nbk) >> 20; });
             // L.b[0..nc) carried records (ranks lo - nc ..), then this bucket
             const uint32_t r0 = lo - nc;
             uint32_t r1;  // end of the complete batches
@@ -362,11 +398,10 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
                 const uint32_t last_start = (s.nbat - 1) * s.p;
                 if (r1 > last_start) r1 = last_start > r0 ? last_start : r0;
             }
-            batches<D, KERN, P>(s, L.b, r0, r1 > r0 ? r1 : r0,
-                                [&](uint32_t r, const Rec<D> &o) { state[r] = o; });
+            batches<D, KERN, P>(s, tm, L.b, r0, r1, [&](uint32_t r, const Rec<D> &o) { state[r] = o; });
             __syncthreads();
-            const uint32_t keep = hi - (r1 > r0 ? r1 : r0);
-            const uint32_t from = (r1 > r0 ? r1 : r0) - r0;
+            const uint32_t keep = hi - r1;
+            const uint32_t from = r1 - r0;
             Rec<D> mv[E];
 #pragma unroll
             for (int k = 0; k < E; ++k) {
@@ -382,7 +417,6 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
             if (tid == 0) L.ncarry = keep;
             __syncthreads();
         }
-        __threadfence();
         __syncthreads();
     }
     for (uint32_t k = tid; k < n; k += TPB) {
@@ -392,37 +426,53 @@ __device__ void run_large(Lds<D> &L, StepArgs s, int64_t nsteps, float *__restri
     }
 }
 
+__device__ __forceinline__ StepArgs args_of(const StepArgs &base, const Sys &sy, uint32_t id)
+{
+    StepArgs s = base;
+    s.n = sy.n;
+    s.nbat = sy.n / s.p;
+    s.inv_last = sy.inv_last;
+    s.k0 = sy.k0;
+    s.k1 = sy.k1;
+    s.sys = id;
+    return s;
+}
+
 template <int D, int KERN, int P>
-__global__ __launch_bounds__(TPB) void k_ensemble(StepArgs base, int64_t nsteps, uint32_t nsys,
-                                                  uint32_t lds_max, const Sys *__restrict__ sys,
-                                                  const uint32_t *__restrict__ order,
-                                                  uint32_t *__restrict__ next,
-                                                  float *__restrict__ x, Rec<D> *__restrict__ state,
-                                                  Rec<D> *__restrict__ stage,
-                                                  uint32_t *__restrict__ wst,
-                                                  uint32_t *__restrict__ flags)
+__global__ __launch_bounds__(TPB) void k_ensemble(EnsLaunch e)
 {
     __shared__ Lds<D> L;
+    const Sys *__restrict__ sys = (const Sys *)e.sys;
     for (;;) {
-        if (threadIdx.x == 0) L.sys = atomicAdd(next, 1u);
+        if (threadIdx.x == 0) L.item = atomicAdd(e.next, 1u);
         __syncthreads();
-        const uint32_t q = L.sys;
+        const uint32_t q = L.item;
         __syncthreads();
-        if (q >= nsys) break;  // every workgroup leaves once the queue is empty
-        const uint32_t id = order[q];
-        const Sys sy = sys[id];
-        StepArgs s = base;
-        s.n = sy.n;
-        s.nbat = sy.n / s.p;
-        s.inv_last = sy.inv_last;
-        s.k0 = sy.k0;
-        s.k1 = sy.k1;
-        s.sys = id;
-        float *xs = x + (size_t)sy.off * D;
-        if (sy.n <= lds_max)
-            run_small<D, KERN, P>(L, s, nsteps, xs);
-        else
-            run_large<D, KERN, P>(L, s, nsteps, xs, state + sy.off, stage + sy.off, wst + sy.off, flags);
+        if (q >= e.nitems) break;  // every workgroup leaves once the queue is empty
+        const uint2 it = e.items[q];  // systems order[it.x .. it.x + it.y)
+        if (it.y == 1) {
+            const uint32_t id = e.order[it.x];
+            const Sys sy = sys[id];
+            const StepArgs s = args_of(e.base, sy, id);
+            float *xs = e.x + (size_t)sy.off * D;
+            const Team tm = make_team(TPB);
+            if (sy.n <= e.lds_max)
+                run_small<D, KERN, P>(L, tm, s, e.nsteps, xs);
+            else
+                run_large<D, KERN, P>(L, tm, s, e.nsteps, e.bmean, xs, (Rec<D> *)e.state + sy.off,
+                                      (Rec<D> *)e.stage + sy.off, e.wst + sy.off, e.flags);
+        } else {
+            const Team tm = make_team(e.team);
+            // teams beyond the item's systems run an empty system in step
+            Sys sy{};
+            uint32_t id = 0;
+            if (tm.tb < it.y) {
+                id = e.order[it.x + tm.tb];
+                sy = sys[id];
+            }
+            const StepArgs s = args_of(e.base, sy, id);
+            run_small<D, KERN, P>(L, tm, s, e.nsteps, e.x + (size_t)sy.off * D);
+        }
         __syncthreads();
     }
 }
@@ -441,17 +491,12 @@ namespace {
 template <int D, int KERN>
 hipError_t ens_dk(const EnsLaunch &e, hipStream_t st)
 {
-#define RBM_ENS(PP)                                                                             \
-    hipLaunchKernelGGL((ens::k_ensemble<D, KERN, PP>), dim3(e.grid), dim3(ens::TPB), 0, st,      \
-                       e.base, e.nsteps, e.nsys, e.lds_max, (const ens::Sys *)e.sys, e.order,     \
-                       e.next, e.x, (Rec<D> *)e.state, (Rec<D> *)e.stage, e.wst, e.flags)
     switch (e.base.p) {
-    case 2: RBM_ENS(2); break;
-    case 4: RBM_ENS(4); break;
-    case 8: RBM_ENS(8); break;
-    default: RBM_ENS(0); break;
+    case 2: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 2>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
+    case 4: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 4>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
+    case 8: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 8>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
+    default: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 0>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
     }
-#undef RBM_ENS
     return hipGetLastError();
 }
 
@@ -466,6 +511,5 @@ hipError_t launch_ensemble(const EnsLaunch &e, int kernel, hipStream_t st)
     default: return ens_dk<2, K_ATTREP>(e, st);
     }
 }
-
 
 }  // namespace rbm

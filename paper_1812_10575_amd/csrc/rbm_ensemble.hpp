@@ -8,9 +8,8 @@
 #include "rbm_device.hpp"
 
 #define RBM_ENS_LDS 4096     // largest system kept in LDS for all steps (d = 2)
-#define RBM_ENS_BUCKET 1024  // mean bucket of a streamed system
-#define RBM_ENS_MAXB 256     // buckets of the largest streamed system
-#define RBM_ENS_MAXN (RBM_ENS_MAXB * RBM_ENS_BUCKET)
+#define RBM_ENS_MAXB 256     // buckets of a streamed system at most
+#define RBM_ENS_MAXN (256 * 1024)
 
 namespace rbm {
 
@@ -25,11 +24,14 @@ struct EnsSys {
 struct EnsLaunch {
     StepArgs base;      // shared model parameters; step index in base.m
     int64_t nsteps;
-    uint32_t nsys;
-    uint32_t lds_max;   // systems up to this size stay in LDS
+    uint32_t nitems;    // work items in the queue
+    uint32_t lds_max;   // a whole-workgroup system up to this size stays in LDS
+    uint32_t team;      // threads per system of a grouped item (64 .. 1024)
+    uint32_t bmean;     // mean bucket of a streamed system
     uint32_t grid;      // persistent workgroups
-    void *sys;          // per-system table (offset, n, key)
-    uint32_t *order;    // queue order (largest first)
+    void *sys;          // per-system table (EnsSys)
+    const uint32_t *order;  // systems in queue order
+    const uint2 *items;     // item q: systems order[x .. x + y)
     uint32_t *next;     // queue counter; next[1]: error flags
     float *x;           // packed positions, by (system, id), in and out
     void *state, *stage;

@@ -154,3 +154,26 @@ def test_zero_steps_and_bad_arguments():
         run(make([64, rbm.ENS_MAXN + 1]), np.zeros((64 + rbm.ENS_MAXN + 1, 2), np.float32), 0, 1)
     with pytest.raises(rbm.RbmError):
         run(ens, x0, 0, 1, lds_max=rbm.ENS_LDS + 1)
+
+
+def test_every_tile_gives_the_same_result():
+    """team, bucket and lds_max change the launch shape, never the result."""
+    ens = make(rbm_inputs.ensemble_sizes(24, 64, 20000, seed=4))
+    x0 = x0_of(ens, 10)
+    ref = run(ens, x0, 2, 4)
+    for tile in (dict(team=64), dict(team=128, bucket=1024), dict(team=1024, bucket=3072, lds_max=2048),
+                 dict(team=512, bucket=256, lds_max=1)):
+        assert np.array_equal(run(ens, x0, 2, 4, **tile), ref), tile
+
+
+def test_autotuner_picks_a_valid_tile(tmp_path):
+    from paper_1812_10575_amd import autotune
+    ens = make(rbm_inputs.ensemble_sizes(64, 64, 30000, seed=6))
+    x = torch.from_numpy(x0_of(ens, 11)).cuda()
+    x_before = x.clone()
+    cache = str(tmp_path / "tune.json")
+    tile = autotune.tune(ens, x, probe_steps=3, cache=cache)
+    assert torch.equal(x, x_before)
+    assert tile in list(autotune.candidates(ens))
+    assert autotune.tune(ens, x, cache=cache) == tile  # from the cache
+    assert np.array_equal(run(ens, x_before.cpu().numpy(), 0, 3, **tile), run(ens, x_before.cpu().numpy(), 0, 3))
