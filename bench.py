@@ -28,6 +28,7 @@ METRIC = "particle-steps/s at N=2^24,p=8; force MSE vs direct sum, plain vs cont
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "attrep3d-n2^24-p8"
 FIELDS = ("d", "kernel", "n", "p", "kparam", "beta", "sigma", "dt", "seed")
+CALIB_COPY_BYTES = 256 << 20
 
 
 def phase_bytes(w: dict) -> dict:
@@ -40,18 +41,102 @@ def phase_bytes(w: dict) -> dict:
     return {"scatter": 2 * rec * n, "split": 2 * rec * n, "sort": 2 * rec * n}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rbm_step_traffic_attrep3d_n2e24_p8.md")
+STEP_SOURCES = ("rbm_kernels.hip", "rbm_device.hpp", "rbm_plan.hpp")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None when the
+    step kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    h = hashlib.sha256()
+    for fn in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1812_10575_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            m = re.match(r"traffic-record: kernel=(\S+) bytes_per_launch=(\d+) source_sha256=([0-9a-f]+)", line)
+            if m and m.group(1) == kernel and m.group(3) == h.hexdigest():
+                return int(m.group(2))
+    return None
+
+
+def p_sweep(args, w, x0) -> dict:
+    """Throughput of the same workload at other batch sizes (10 timed steps each)."""
+    import torch
+    import paper_1812_10575_amd as rbm
+    out = {}
+    xt = torch.from_numpy(x0).cuda()
+    for p in (2, 4, 8, 16, 32):
+        prm = rbm.Params(**{**{k: w[k] for k in FIELDS}, "p": p})
+        ctx = rbm.rbm_init(prm, xt)
+        rbm.rbm_run(ctx, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rbm.rbm_run(ctx, 10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rbm.rbm_check(ctx)
+        out[str(p)] = round(w["n"] * 10 / dt, -6)
+        del ctx
+    return {"unit": "particle-steps/s", "steps": 10, "value": out}
+
+
+# FP32 operations per ordered pair of the attraction-repulsion kernel in 3-D:
+# difference 3, squared norm 3 FMA (6), + a 1, reciprocal 1, - 1 1,
+# scaled accumulation 3 FMA (6)
+DIRECT_FLOPS_PER_PAIR = 18
+FP32_PEAK_TFLOPS = 157.3
+
+
+def direct_rate(w, x0) -> dict:
+    """The exact O(N^2) force (direct_forces) at N = 2^20 for a subset of
+    2^16 target particles: pair evaluations per second and FP32 FLOP/s."""
+    import numpy as np
+    import torch
+    import paper_1812_10575_amd as rbm
+    n = 1 << 20
+    prm = rbm.Params(**{**{k: w[k] for k in FIELDS}, "n": n})
+    x = torch.from_numpy(np.ascontiguousarray(x0[:n])).cuda()
+    ids = torch.arange(0, n, 16, dtype=torch.int32, device="cuda")
+    rbm.direct_forces(prm, x, ids)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        rbm.direct_forces(prm, x, ids)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    pairs = ids.numel() * (n - 1)
+    tf = pairs * DIRECT_FLOPS_PER_PAIR / dt / 1e12
+    return {"n": n, "targets": ids.numel(), "seconds": round(dt, 5), "pairs_per_s": pairs / dt,
+            "roofline": {"bound": "fp32", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP32_PEAK_TFLOPS, 4), "flops_per_pair": DIRECT_FLOPS_PER_PAIR}}
+
+
 def cpu_baseline(w: dict, x0) -> dict:
+    """The FP64 oracle on this host: whole steps of the same workload,
+    repeated until at least 10 s have passed."""
     import numpy as np
     import oracle as ora
     o = ora.Params(d=w["d"], kernel=w["kernel"], kparam=w["kparam"], beta=w["beta"],
                    sigma=w["sigma"], dt=w["dt"], seed=w["seed"])
     x = x0.astype(np.float64)
     slots = np.arange(w["n"], dtype=np.uint32)
+    steps = 0
     t0 = time.perf_counter()
-    ora.rbm_step(o, w["p"], 0, x, slots)
-    t = time.perf_counter() - t0
-    return {"value": w["n"] / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full step of the same workload (N={w['n']}, p={w['p']}), "
+    while True:
+        x, slots = ora.rbm_step(o, w["p"], steps, x, slots)
+        steps += 1
+        t = time.perf_counter() - t0
+        if t >= 10.0:
+            break
+    return {"value": w["n"] * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full steps of the same workload (N={w['n']}, p={w['p']}), "
                       f"single-threaded FP64 C oracle, {t:.1f} s"}
 
 
@@ -172,7 +257,10 @@ def main() -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--mse-snap-every", type=int, default=25)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble part")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the p sweep and the direct-sum rate")
     ap.add_argument("--retune", action="store_true", help="ignore the ensemble autotune cache")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy first (a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -195,6 +283,13 @@ def main() -> int:
     x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib_copy:
+        a = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = rbm.rbm_init(prm, torch.from_numpy(x0).to(dev))
     stream = torch.cuda.current_stream()
 
@@ -222,7 +317,7 @@ def main() -> int:
     if dom in pb:
         ach = pb[dom] / (phase_ms[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                 "algorithmic_bytes_per_launch": pb[dom]}
     else:
         roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
@@ -249,6 +344,9 @@ def main() -> int:
                    "a": w["kparam"], "beta": w["beta"], "sigma": w["sigma"], "dt": w["dt"]},
         "roofline": roof,
     }
+    if not args.no_sweep:
+        out["p_sweep"] = p_sweep(args, w, x0)
+        out["direct"] = direct_rate(w, x0)
     if not args.no_mse:
         out["force_mse"] = force_mse(args)
     if not args.no_ensemble:
