@@ -149,3 +149,33 @@ def test_pair_sampler():
     assert stats.chisquare(np.bincount(pr[:, 1], minlength=50)).pvalue > 1e-4
     assert stats.chisquare(np.bincount(pr[:, 2], minlength=50)).pvalue > 1e-4
     assert not np.array_equal(pr, cv.sample_pairs(1, 4000, 3, 50))
+
+
+def test_forward_of_a_hand_built_network():
+    """A network whose output is known in closed form: hidden unit 0 of layer
+    1 carries x0 + 2 x1 + 0.5, hidden unit 3 of layer 2 carries
+    -1.5 gelu(z1_0) + 0.25, and output 7 reads 2 gelu(z2_3) - 1; every other
+    output is its bias."""
+    th = np.zeros(cv.NPARAM)
+    p = cv.unpack(th)
+    p["W1"][0] = [1.0, 2.0]
+    p["b1"][0] = 0.5
+    p["b1"][1:] = -40.0            # other layer-1 units: gelu(-40) = 0 up to 1e-300
+    p["W2"][3, 0] = -1.5
+    p["b2"][3] = 0.25
+    p["b2"][np.arange(64) != 3] = -40.0
+    p["W3"][7, 3] = 2.0
+    p["b3"][:] = np.arange(32) * 0.01
+    p["b3"][7] = -1.0
+    x = np.array([[0.3, -0.7], [1.1, 0.4], [-2.0, 0.9]])
+    phi = lambda z: 0.5 * (1 + np.vectorize(math.erf)(z / math.sqrt(2)))
+    z1 = x[:, 0] + 2 * x[:, 1] + 0.5
+    z2 = -1.5 * z1 * phi(z1) + 0.25
+    o7 = 2 * z2 * phi(z2) - 1.0
+    out = cv.forward(th, x)[4]
+    np.testing.assert_allclose(out[:, 7], o7, rtol=1e-13, atol=1e-13)
+    others = np.delete(out, 7, axis=1)
+    np.testing.assert_allclose(others, np.broadcast_to(np.delete(np.arange(32) * 0.01, 7), others.shape),
+                               atol=1e-13)
+    # the feature layout: output 7 is component k = 0, rank r = 7
+    assert np.array_equal(cv.features(th, x)[:, 0, 7], out[:, 7])
