@@ -20,8 +20,8 @@ Given the division, the first term is exact; the second is RBM-1 applied to
 K_res, so by Lemma 3.1 (valid for general K(x, y)) the force is unbiased for
 any weights and its variance is (1/(p-1) - 1/(N-1)) Lambda_i[K_res].
 
-Network: 2 -> 64 -> 64 -> 32, GELU(z) = z Phi(z) after the two hidden
-layers, linear output.  Parameter vector of one net, in this order:
+Network: 2 -> 64 -> 64 -> 32, GELU (tanh form) after the two hidden layers,
+linear output.  Parameter vector of one net, in this order:
 W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32] (6432 values).
 
 `use_bf16=True` rounds (to nearest even) exactly the operands the GPU feeds
@@ -64,17 +64,27 @@ def bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+GELU_K = 2.0 * math.sqrt(2.0 / math.pi)
+GELU_C = 0.044715
+
+
+def _sigma_v(z):
+    z = np.asarray(z, np.float64)
+    v = GELU_K * z * (1.0 + GELU_C * z * z)
+    from scipy.special import expit  # the logistic function 1 / (1 + e^-v)
+    return expit(v)
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+    """GELU in its tanh form, 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
+    evaluated as z sigma(v), v = 2 sqrt(2/pi) z (1 + 0.044715 z^2)."""
+    return np.asarray(z, np.float64) * _sigma_v(z)
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
-
-
-def _erf(x):
-    from scipy.special import erf
-    return erf(x)
+    z = np.asarray(z, np.float64)
+    s = _sigma_v(z)
+    return s + z * s * (1.0 - s) * GELU_K * (1.0 + 3.0 * GELU_C * z * z)
 
 
 def forward(theta, x, use_bf16=False):

@@ -762,12 +762,16 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
         if (he == hipSuccess) he = hipGraphLaunch(ge, cs);
         if (he == hipSuccess) he = hipEventRecord(ev1, cs);
         if (he == hipSuccess) he = hipStreamWaitEvent(hs, ev1, 0);
-        if (cs) hipStreamSynchronize(cs);
-        if (ge) hipGraphExecDestroy(ge);
-        if (g) hipGraphDestroy(g);
-        if (ev0) hipEventDestroy(ev0);
-        if (ev1) hipEventDestroy(ev1);
-        if (cs) hipStreamDestroy(cs);
+        // tear-down: the first error, if any, is the one reported
+        hipError_t te = hipSuccess;
+        auto keep = [&](hipError_t x) { if (te == hipSuccess) te = x; };
+        if (cs) keep(hipStreamSynchronize(cs));
+        if (ge) keep(hipGraphExecDestroy(ge));
+        if (g) keep(hipGraphDestroy(g));
+        if (ev0) keep(hipEventDestroy(ev0));
+        if (ev1) keep(hipEventDestroy(ev1));
+        if (cs) keep(hipStreamDestroy(cs));
+        if (he == hipSuccess) he = te;
         if (he != hipSuccess) return hip_fail(he, "ensemble graph");
     }
     uint32_t flags = 0;

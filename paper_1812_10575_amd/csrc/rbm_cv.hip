@@ -38,15 +38,28 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16 *p)
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-__device__ __forceinline__ float gelu(float z)
+// GELU in its tanh form, 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
+// written as z sigma(v) with v = 2 sqrt(2/pi) z (1 + 0.044715 z^2): one
+// exponential and one reciprocal on the VALU.
+constexpr float GELU_K = 1.5957691216057308f;  // 2 sqrt(2/pi)
+constexpr float GELU_C = 0.044715f;
+
+__device__ __forceinline__ float gelu_sig(float z)
 {
-    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+    const float v = GELU_K * z * fmaf(GELU_C, z * z, 1.0f);
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-v));
 }
 
+__device__ __forceinline__ float gelu(float z)
+{
+    return z * gelu_sig(z);
+}
+
+// d/dz [z sigma(v)] = sigma + z sigma (1 - sigma) v'(z), v' = K (1 + 3 C z^2)
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * 0.39894228040143268f * __expf(-0.5f * z * z);
+    const float sg = gelu_sig(z);
+    return fmaf(z * sg * (1.0f - sg), GELU_K * fmaf(3.0f * GELU_C, z * z, 1.0f), sg);
 }
 
 struct NetP {
@@ -214,21 +227,109 @@ __global__ __launch_bounds__(256) void k_features(const float *__restrict__ mast
     }
 }
 
+// ---------------------------------------------------------------------------
+// inference inside the step: the weights of a net are staged in LDS once per
+// workgroup (rows padded to WP so that the 16 lanes of a fragment read hit
+// different banks) and every wavefront runs 16-sample tiles on its own,
+// with no workgroup barrier between the layers.
+// ---------------------------------------------------------------------------
+constexpr int WP = 72;
+
+struct __align__(16) NetLds {
+    __bf16 W2[64][WP];  // [out][in]
+    __bf16 W3[32][WP];
+    float w1[64][2];
+    float b1[64], b2[64], b3[32];
+};
+
+__device__ void stage_net(NetLds &N, const float *master, const __bf16 *wb, int net)
+{
+    const NetP np = net_of(master, wb, net);
+    for (int e = threadIdx.x; e < 64 * 8; e += blockDim.x) {
+        const int r = e >> 3, c = (e & 7) * 8;
+        *reinterpret_cast<bf16x8 *>(&N.W2[r][c]) = ld8(np.W2 + r * 64 + c);
+    }
+    for (int e = threadIdx.x; e < 32 * 8; e += blockDim.x) {
+        const int r = e >> 3, c = (e & 7) * 8;
+        *reinterpret_cast<bf16x8 *>(&N.W3[r][c]) = ld8(np.W3 + r * 64 + c);
+    }
+    for (int e = threadIdx.x; e < 128; e += blockDim.x) N.w1[e >> 1][e & 1] = np.p[CV_OW1 + e];
+    for (int e = threadIdx.x; e < 64; e += blockDim.x) {
+        N.b1[e] = np.p[CV_OB1 + e];
+        N.b2[e] = np.p[CV_OB2 + e];
+    }
+    for (int e = threadIdx.x; e < 32; e += blockDim.x) N.b3[e] = np.p[CV_OB3 + e];
+}
+
+// One wavefront, 16 samples: lane l brings sample l % 16 (x0, x1) and gets
+// out[t][i] = O[4 (l / 16) + i][16 t + l % 16] (t < 2, i < 4).  Layer 1 is
+// computed straight into the A fragments (lane l: hidden units 32 ks +
+// 8 (l / 16) + i of its sample); H2 goes through the wave's own LDS rows to
+// change from the accumulator layout to the A layout.  Same operations and
+// roundings as fwd16.
+__device__ __forceinline__ void fwd_tile(const NetLds &N, float x0, float x1, __bf16 (*H2)[WP],
+                                         float (&out)[2][4])
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+    bf16x8 a1[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 32 * ks + 8 * g + i;
+            const float z = fmaf(N.w1[k][0], x0, fmaf(N.w1[k][1], x1, N.b1[k]));
+            a1[ks][i] = (__bf16)gelu(z);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) acc = mfma(a1[ks], ld8(&N.W2[16 * t + col][32 * ks + 8 * g]), acc);
+        const float b = N.b2[16 * t + col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) H2[4 * g + i][16 * t + col] = (__bf16)gelu(acc[i] + b);
+    }
+    // the wave's own LDS writes are seen by its later reads (LDS operations of
+    // one wavefront complete in order); keep the compiler from moving them
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            acc = mfma(ld8(&H2[col][32 * ks + 8 * g]), ld8(&N.W3[16 * t + col][32 * ks + 8 * g]), acc);
+        const float b = N.b3[16 * t + col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[t][i] = acc[i] + b;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Partial sums of c(X_j) over the state records (slot order, pending noise
-// added): part[wg][32] in FP64, workgroup wg taking rounds of 64 records
-// wg, wg + G, ...
+// added): part[wg][32] in FP64.  Workgroup wg takes tiles of 256 records wg,
+// wg + G, ...; each lane sums its samples in tile order, then the lanes and
+// waves of the workgroup are added in a fixed order.
+struct SumLds {
+    NetLds net;
+    float X[256][2];
+    __bf16 H2[4][16][WP];
+    double red[4][4][CV_NO];
+};
+
 __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restrict__ state,
                                               const float *__restrict__ master,
                                               const __bf16 *__restrict__ wb,
                                               double *__restrict__ part)
 {
-    __shared__ FwdLds L;
-    const int w = threadIdx.x >> 6;
-    const NetP np = net_of(master, wb, 1);
-    double acc = 0.0;
-    for (uint32_t base = blockIdx.x * 64; base < s.n; base += gridDim.x * 64) {
-        if (threadIdx.x < 64) {
-            const uint32_t k = base + threadIdx.x;
+    __shared__ SumLds L;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+    stage_net(L.net, master, wb, 1);
+    double acc[2] = {0.0, 0.0};
+    for (uint32_t base = blockIdx.x * 256; base < s.n; base += gridDim.x * 256) {
+        {
+            const uint32_t k = base + tid;
             float xy[2] = {0.0f, 0.0f};
             if (k < s.n) {
                 Rec<2> r = state[k];
@@ -236,52 +337,72 @@ __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restri
                 xy[0] = r.x[0];
                 xy[1] = r.x[1];
             }
-            L.X[threadIdx.x][0] = xy[0];
-            L.X[threadIdx.x][1] = xy[1];
+            L.X[tid][0] = xy[0];
+            L.X[tid][1] = xy[1];
         }
         __syncthreads();
-        fwd16(np, &L.X[16 * w][0], &L.H1[16 * w][0], &L.H2[16 * w][0], nullptr, nullptr,
-              &L.O[16 * w][0], CV_NO);
-        if (threadIdx.x < CV_NO) {
-            const uint32_t cnt = min(64u, s.n - base);
-            for (uint32_t r = 0; r < cnt; ++r) acc += (double)L.O[r][threadIdx.x];
+#pragma unroll 1
+        for (int mt = 0; mt < 4; ++mt) {
+            const int m = 64 * w + 16 * mt;
+            float out[2][4];
+            fwd_tile(L.net, L.X[m + col][0], L.X[m + col][1], L.H2[w], out);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (base + m + 4 * g + i < s.n) {
+                    acc[0] += (double)out[0][i];
+                    acc[1] += (double)out[1][i];
+                }
         }
         __syncthreads();
     }
-    if (threadIdx.x < CV_NO) part[blockIdx.x * CV_NO + threadIdx.x] = acc;
+    L.red[w][g][col] = acc[0];
+    L.red[w][g][16 + col] = acc[1];
+    __syncthreads();
+    if (tid < CV_NO) {
+        double t = 0.0;
+        for (int ww = 0; ww < 4; ++ww)
+            for (int gg = 0; gg < 4; ++gg) t += L.red[ww][gg][tid];
+        part[blockIdx.x * CV_NO + tid] = t;
+    }
 }
 
-// S[f] = sum over workgroups of part[wg][f], in workgroup order.
-__global__ __launch_bounds__(64) void k_csum_final(uint32_t nwg, const double *__restrict__ part,
-                                                   double *__restrict__ S)
+// Thread (f, c) of the 32 x 32 block sums workgroups c, c + 32, ... in
+// order; thread f of the first 32 then sums the 32 chunk sums in order.
+__global__ __launch_bounds__(1024) void k_csum_final(uint32_t nwg, const double *__restrict__ part,
+                                                     double *__restrict__ S)
 {
-    const uint32_t f = threadIdx.x;
-    if (f >= CV_NO) return;
+    __shared__ double chunk[32][CV_NO + 1];
+    const uint32_t f = threadIdx.x % CV_NO, c = threadIdx.x / CV_NO;
     double acc = 0.0;
-    for (uint32_t g = 0; g < nwg; ++g) acc += part[g * CV_NO + f];
-    S[f] = acc;
+    for (uint32_t g = c; g < nwg; g += 32) acc += part[g * CV_NO + f];
+    chunk[c][f] = acc;
+    __syncthreads();
+    if (threadIdx.x < CV_NO) {
+        double t = 0.0;
+        for (uint32_t k = 0; k < 32; ++k) t += chunk[k][threadIdx.x];
+        S[threadIdx.x] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // control-variate batch force over sorted records
 // ---------------------------------------------------------------------------
-// Workgroup b < G-1 takes batches [b qb, min((b+1) qb, nbat-1)); the last
-// workgroup takes the last batch (p plus the leftover ranks).  qb = 128 / p,
-// so a workgroup holds at most CV_MAXR = 128 records (p <= 64).
+// Tile b < T-1 holds batches [b qb, min((b+1) qb, nbat-1)); tile T-1 holds
+// the last batch (p plus the leftover ranks).  qb = 128 / p, so a tile has at
+// most CV_MAXR = 128 records (p <= 64).  Persistent workgroups take tiles b,
+// b + G, ... with both nets staged in LDS once.
 struct BatchLds {
+    NetLds net[2];
     float X[CV_MAXR][2];
     uint32_t id[CV_MAXR];
-    float A[CV_MAXR][CV_NO];
-    float C[CV_MAXR][CV_NO];
-    float sn[CV_NO];   // S / (N - 1)
-    __bf16 H1[64][64];
-    __bf16 H2[64][64];
-    float Xt[64][2];
-    float O[64][CV_NO];
+    float A[CV_MAXR][CV_NO + 1];  // padded rows: one record per lane hits distinct banks
+    float C[CV_MAXR][CV_NO + 1];
+    __bf16 H2[4][16][WP];
+    float sn[CV_NO];  // S / (N - 1)
 };
 
 template <int KERN>
-__global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb,
+__global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint32_t ntiles,
                                                   const Rec<2> *__restrict__ sorted,
                                                   const float *__restrict__ master,
                                                   const __bf16 *__restrict__ wb,
@@ -289,90 +410,102 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb,
                                                   Rec<2> *__restrict__ dst, float *__restrict__ fout)
 {
     __shared__ BatchLds L;
-    const int tid = threadIdx.x, w = tid >> 6;
-    uint32_t q0, q1;
-    if (blockIdx.x == gridDim.x - 1) {
-        q0 = s.nbat - 1;
-        q1 = s.nbat;
-    } else {
-        q0 = blockIdx.x * qb;
-        q1 = min(q0 + qb, s.nbat - 1);
-    }
-    const uint32_t r0 = q0 * s.p;
-    const uint32_t r1 = (q1 == s.nbat) ? s.n : q1 * s.p;
-    const uint32_t nr = r1 - r0;  // <= CV_MAXR by the launch geometry
-    for (uint32_t l = tid; l < nr; l += 256) {
-        const Rec<2> r = sorted[r0 + l];
-        L.X[l][0] = r.x[0];
-        L.X[l][1] = r.x[1];
-        L.id[l] = r.id;
-    }
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+    stage_net(L.net[0], master, wb, 0);
+    stage_net(L.net[1], master, wb, 1);
     if (tid < CV_NO) L.sn[tid] = (float)(S[tid] / (double)(s.n - 1));
-    __syncthreads();
-    // a and c of every record, 64 at a time
-    for (uint32_t base = 0; base < nr; base += 64) {
-        if (tid < 128) {
-            const uint32_t t = tid >> 1, c = tid & 1;
-            L.Xt[t][c] = base + t < nr ? L.X[base + t][c] : 0.0f;
+    const float inv_n1 = 1.0f / (float)(s.n - 1);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint32_t q0, q1;
+        if (tile == ntiles - 1) {
+            q0 = s.nbat - 1;
+            q1 = s.nbat;
+        } else {
+            q0 = tile * qb;
+            q1 = min(q0 + qb, s.nbat - 1);
+        }
+        const uint32_t r0 = q0 * s.p;
+        const uint32_t r1 = (q1 == s.nbat) ? s.n : q1 * s.p;
+        const uint32_t nr = r1 - r0;  // <= CV_MAXR by the tiling
+        __syncthreads();              // the previous tile is done with the LDS
+        if (tid < CV_MAXR) {
+            float xy[2] = {0.0f, 0.0f};
+            uint32_t id = 0;
+            if ((uint32_t)tid < nr) {
+                const Rec<2> r = sorted[r0 + tid];
+                xy[0] = r.x[0];
+                xy[1] = r.x[1];
+                id = r.id;
+            }
+            L.X[tid][0] = xy[0];
+            L.X[tid][1] = xy[1];
+            L.id[tid] = id;
         }
         __syncthreads();
+        // a and c of the tile's records: wave w takes rows 32 w .. 32 w + 31
+#pragma unroll 1
         for (int net = 0; net < 2; ++net) {
-            const NetP np = net_of(master, wb, net);
-            fwd16(np, &L.Xt[16 * w][0], &L.H1[16 * w][0], &L.H2[16 * w][0], nullptr, nullptr,
-                  &L.O[16 * w][0], CV_NO);
-            for (uint32_t e = tid; e < 64 * CV_NO; e += 256) {
-                const uint32_t t = e / CV_NO, f = e % CV_NO;
-                if (base + t < nr) (net == 0 ? L.A : L.C)[base + t][f] = L.O[t][f];
+            float(*dstf)[CV_NO + 1] = net == 0 ? L.A : L.C;
+#pragma unroll 1
+            for (int mt = 0; mt < 2; ++mt) {
+                const int m = 32 * w + 16 * mt;
+                float out[2][4];
+                fwd_tile(L.net[net], L.X[m + col][0], L.X[m + col][1], L.H2[w], out);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) dstf[m + 4 * g + i][16 * t + col] = out[t][i];
             }
-            __syncthreads();
         }
-    }
-    // forces, one thread per record
-    for (uint32_t l = tid; l < nr; l += 256) {
-        const uint32_t r = r0 + l;
-        uint32_t bs, be;
-        batch_of(s, r, bs, be);
-        const float *a = L.A[l];
-        float f[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) acc = fmaf(a[16 * k + rr], L.sn[16 * k + rr] - L.C[l][16 * k + rr] * (1.0f / (float)(s.n - 1)), acc);
-            f[k] = acc;
-        }
-        const float xi[2] = {L.X[l][0], L.X[l][1]};
-        float res[2] = {0.0f, 0.0f};
-        for (uint32_t j = bs; j < be; ++j) {
-            if (j == r) continue;
-            const uint32_t lj = j - r0;
-            float kv[2] = {0.0f, 0.0f};
-            add_pair<2, KERN>(xi, L.X[lj], s.a, kv);
+        __syncthreads();
+        // forces, one thread per record
+        if ((uint32_t)tid < nr) {
+            const uint32_t l = tid, r = r0 + l;
+            uint32_t bs, be;
+            batch_of(s, r, bs, be);
+            const float *a = L.A[l];
+            float f[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                float dot = 0.0f;
+                float acc = 0.0f;
 #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) dot = fmaf(a[16 * k + rr], L.C[lj][16 * k + rr], dot);
-                res[k] += kv[k] - dot;
+                for (int rr = 0; rr < 16; ++rr)
+                    acc = fmaf(a[16 * k + rr], L.sn[16 * k + rr] - L.C[l][16 * k + rr] * inv_n1, acc);
+                f[k] = acc;
             }
-        }
-        const float inv = (be - bs == s.p) ? s.inv_p1 : s.inv_last;
-        float x[2] = {xi[0], xi[1]};
-        f[0] = fmaf(res[0], inv, f[0]);
-        f[1] = fmaf(res[1], inv, f[1]);
-        const uint32_t id = L.id[l];
-        if (fout) {
-            if (id < s.n) {
-                fout[(size_t)id * 2] = f[0];
-                fout[(size_t)id * 2 + 1] = f[1];
+            const float xi[2] = {L.X[l][0], L.X[l][1]};
+            float res[2] = {0.0f, 0.0f};
+            for (uint32_t j = bs; j < be; ++j) {
+                if (j == r) continue;
+                const uint32_t lj = j - r0;
+                float kv[2] = {0.0f, 0.0f};
+                add_pair<2, KERN>(xi, L.X[lj], s.a, kv);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    float dot = 0.0f;
+#pragma unroll
+                    for (int rr = 0; rr < 16; ++rr) dot = fmaf(a[16 * k + rr], L.C[lj][16 * k + rr], dot);
+                    res[k] += kv[k] - dot;
+                }
             }
-        } else {
-            drift_update<2>(s, x, f);
-            Rec<2> o;
-            o.x[0] = x[0];
-            o.x[1] = x[1];
-            o.id = id;
-            dst[r] = o;
+            const float inv = (be - bs == s.p) ? s.inv_p1 : s.inv_last;
+            float x[2] = {xi[0], xi[1]};
+            f[0] = fmaf(res[0], inv, f[0]);
+            f[1] = fmaf(res[1], inv, f[1]);
+            const uint32_t id = L.id[l];
+            if (fout) {
+                if (id < s.n) {
+                    fout[(size_t)id * 2] = f[0];
+                    fout[(size_t)id * 2 + 1] = f[1];
+                }
+            } else {
+                drift_update<2>(s, x, f);
+                Rec<2> o;
+                o.x[0] = x[0];
+                o.x[1] = x[1];
+                o.id = id;
+                dst[r] = o;
+            }
         }
     }
 }
@@ -648,8 +781,17 @@ __global__ __launch_bounds__(256) void k_reduce_adam(uint32_t nwg, const float *
         *loss_out = l;
     }
     if (q >= 2 * CV_NP) return;
+    // in workgroup order, 16 loads in flight at a time
     float gs = 0.0f;
-    for (uint32_t g = 0; g < nwg; ++g) gs += gpart[(size_t)g * 2 * CV_NP + q];
+    uint32_t g = 0;
+    for (; g + 16 <= nwg; g += 16) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = gpart[(size_t)(g + k) * 2 * CV_NP + q];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) gs += v[k];
+    }
+    for (; g < nwg; ++g) gs += gpart[(size_t)g * 2 * CV_NP + q];
     if (grad_out) grad_out[q] = gs;
     if (adam) {
         const float m = 0.9f * am[q] + 0.1f * gs;
@@ -689,10 +831,10 @@ hipError_t cv_launch_features(const float *master, const __bf16 *wb, const float
 hipError_t cv_launch_csum(const StepArgs &s, const void *state, const float *master,
                           const __bf16 *wb, double *part, double *S, hipStream_t st)
 {
-    const uint32_t g = min((s.n + 63) / 64, (uint32_t)CV_SUM_WG);
+    const uint32_t g = min((s.n + 255) / 256, (uint32_t)CV_SUM_WG);
     hipLaunchKernelGGL(cvk::k_csum, dim3(g), dim3(256), 0, st, s, (const Rec<2> *)state, master, wb,
                        part);
-    hipLaunchKernelGGL(cvk::k_csum_final, dim3(1), dim3(64), 0, st, g, part, S);
+    hipLaunchKernelGGL(cvk::k_csum_final, dim3(1), dim3(1024), 0, st, g, part, S);
     return hipGetLastError();
 }
 
@@ -700,10 +842,21 @@ hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, co
                            const __bf16 *wb, const double *S, void *dst, float *fout, hipStream_t st)
 {
     const uint32_t qb = cv_batches_per_wg(s.p);
-    const dim3 g((s.nbat - 1 + qb - 1) / qb + 1);
+    const uint32_t ntiles = (s.nbat - 1 + qb - 1) / qb + 1;
     if (kernel != K_GAUSS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cvk::k_cv_batch<K_GAUSS>, g, dim3(256), 0, st, s, qb, (const Rec<2> *)sorted,
-                       master, wb, S, (Rec<2> *)dst, fout);
+    static int resident = 0;  // workgroups that fit on the device at once
+    if (resident == 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cvk::k_cv_batch<K_GAUSS>, 256, 0);
+        if (e != hipSuccess) return e;
+        resident = cus * (per > 0 ? per : 1);
+    }
+    const uint32_t g = min(ntiles, (uint32_t)resident);
+    hipLaunchKernelGGL(cvk::k_cv_batch<K_GAUSS>, dim3(g), dim3(256), 0, st, s, qb, ntiles,
+                       (const Rec<2> *)sorted, master, wb, S, (Rec<2> *)dst, fout);
     return hipGetLastError();
 }
 

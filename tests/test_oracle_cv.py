@@ -24,6 +24,17 @@ def thetas():
     return rand_theta(3), rand_theta(4)
 
 
+def test_gelu_is_the_tanh_form_and_close_to_the_exact_one():
+    """Against torch's own tanh-form GELU, and within the known error of that
+    form (< 5e-4) of the exact z Phi(z)."""
+    torch = pytest.importorskip("torch")
+    z = np.linspace(-7, 7, 2801)
+    want = torch.nn.functional.gelu(torch.tensor(z, dtype=torch.float64), approximate="tanh").numpy()
+    np.testing.assert_allclose(cv.gelu(z), want, rtol=1e-14, atol=1e-15)
+    exact = 0.5 * z * (1 + np.vectorize(math.erf)(z / math.sqrt(2)))
+    assert np.max(np.abs(cv.gelu(z) - exact)) < 5e-4
+
+
 def test_gelu_closed_forms():
     assert cv.gelu(np.array(0.0)) == 0.0
     assert cv.gelu_grad(np.array(0.0)) == pytest.approx(0.5, abs=1e-15)
@@ -155,7 +166,7 @@ def test_forward_of_a_hand_built_network():
     """A network whose output is known in closed form: hidden unit 0 of layer
     1 carries x0 + 2 x1 + 0.5, hidden unit 3 of layer 2 carries
     -1.5 gelu(z1_0) + 0.25, and output 7 reads 2 gelu(z2_3) - 1; every other
-    output is its bias."""
+    output is its bias (gelu written here in its tanh form)."""
     th = np.zeros(cv.NPARAM)
     p = cv.unpack(th)
     p["W1"][0] = [1.0, 2.0]
@@ -168,7 +179,7 @@ def test_forward_of_a_hand_built_network():
     p["b3"][:] = np.arange(32) * 0.01
     p["b3"][7] = -1.0
     x = np.array([[0.3, -0.7], [1.1, 0.4], [-2.0, 0.9]])
-    phi = lambda z: 0.5 * (1 + np.vectorize(math.erf)(z / math.sqrt(2)))
+    phi = lambda z: 0.5 * (1 + np.tanh(math.sqrt(2 / math.pi) * (z + 0.044715 * z ** 3)))
     z1 = x[:, 0] + 2 * x[:, 1] + 0.5
     z2 = -1.5 * z1 * phi(z1) + 0.25
     o7 = 2 * z2 * phi(z2) - 1.0
