@@ -170,7 +170,12 @@ def force_mse(args) -> dict:
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ids = torch.from_numpy(np.random.default_rng(7).choice(n, 1 << 16, replace=False).astype(np.int32)).cuda()
-    fdir = rbm.direct_forces(mk(), x, ids)
+    fdir, m2 = rbm.direct_moments(mk(), x, ids)
+    # Lemma 3.1: E|F^RBM - F|^2 = (1/(p-1) - 1/(N-1)) Lambda_i,
+    # Lambda_i = (N-1)/(N-2) (m2_i - |F_i|^2)
+    f64 = fdir.double()
+    lam = (n - 1) / (n - 2) * (m2.double() - (f64 * f64).sum(dim=1))
+    pred_plain = float(((1.0 / (w["p"] - 1) - 1.0 / (n - 1)) * lam).mean())
 
     def mse_of(ctx):
         acc = 0.0
@@ -199,7 +204,7 @@ def force_mse(args) -> dict:
     plain_pp = rbm.rbm_init(mk(p=pp), x)
     mse_pp = mse_of(plain_pp)
     out = {"workload": "gauss2d-n2^22-p2", "n": n, "p": 2, "subset": int(ids.numel()), "divisions": 16,
-           "mse_plain": mse_plain, "mse_cv": mse_cv, "gain": gain,
+           "mse_plain": mse_plain, "mse_plain_lemma_3_1": pred_plain, "mse_cv": mse_cv, "gain": gain,
            "train": {"pairs": args.train_steps * args.train_batch, "adam_steps": args.train_steps,
                      "batch": args.train_batch, "seconds": round(t_train, 3),
                      "loss_first": float(losses[:16].mean().cpu()), "loss_last": float(losses[-16:].mean().cpu())},

@@ -259,6 +259,14 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
 rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t *d_ids,
                          int64_t nids, float *d_f, void *stream);
 
+/* direct_forces plus d_m2[t] = 1/(N-1) sum_{j != i} |K(X_i - X_j)|^2 for the
+ * same particles ([nids] FP32, FP64 sums).  With F_i the exact force, the
+ * variance of Lemma 3.1 is Lambda_i = (N-1)/(N-2) (m2_i - |F_i|^2), and the
+ * RBM-1 force error has E|F_i^RBM - F_i|^2 = (1/(p-1) - 1/(N-1)) Lambda_i
+ * when p divides N.  An id >= N gives NaN outputs. */
+rbm_status direct_moments(const rbm_params *prm, const float *d_x, const uint32_t *d_ids,
+                          int64_t nids, float *d_f, float *d_m2, void *stream);
+
 /* One step of the fully coupled system with the update and NOISE stream of
  * RBM-1 step `step`: d_x_out = d_x + dt (-beta d_x + F) + sigma sqrt(dt) z.
  * d_x_out must not alias d_x. */

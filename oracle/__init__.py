@@ -72,6 +72,7 @@ def _load():
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.ora_rbm_forces.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, f64p, u32p, f64p]
     lib.ora_direct_forces.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p]
+    lib.ora_direct_moments.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p, f64p]
     lib.ora_rbm_step.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, f64p, u32p]
     lib.ora_rbm_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_int64, f64p, u32p]
@@ -165,6 +166,20 @@ def direct_forces(prm: Params, x, ids=None) -> np.ndarray:
     _load().ora_direct_forces(ctypes.byref(prm.c()), n, _p(xv, ctypes.c_double),
                               _p(iv, ctypes.c_uint32), iv.size, _p(f, ctypes.c_double))
     return f
+
+
+def direct_moments(prm: Params, x, ids=None):
+    """(F, m2): the exact force of eq. (1.2) and m2_i = 1/(N-1) sum_{j != i}
+    |K(X_i - X_j)|^2, so that Lambda_i of Lemma 3.1 is
+    (N-1)/(N-2) (m2_i - |F_i|^2)."""
+    xv = _f64(x)
+    n = xv.shape[0]
+    iv = _u32(np.arange(n) if ids is None else ids)
+    f = np.zeros((iv.size, prm.d), np.float64)
+    m2 = np.zeros(iv.size, np.float64)
+    _load().ora_direct_moments(ctypes.byref(prm.c()), n, _p(xv, ctypes.c_double), _p(iv, ctypes.c_uint32),
+                               iv.size, _p(f, ctypes.c_double), _p(m2, ctypes.c_double))
+    return f, m2
 
 
 def rbm_step(prm: Params, p: int, m: int, x, slots):

@@ -247,6 +247,32 @@ void ora_direct_forces(const ora_params *prm, int64_t n, const double *x,
     }
 }
 
+/* The same sums plus the second moment m2_i = 1/(N-1) sum_{j != i}
+ * |K(X_i - X_j)|^2, from which the variance of Lemma 3.1 follows:
+ *   Lambda_i = 1/(N-2) sum_{j != i} |K(X_i - X_j) - F_i|^2
+ *            = (N-1)/(N-2) (m2_i - |F_i|^2). */
+void ora_direct_moments(const ora_params *prm, int64_t n, const double *x,
+                        const uint32_t *ids, int64_t nids, double *f, double *m2)
+{
+    const int d = prm->d;
+    for (int64_t t = 0; t < nids; ++t) {
+        const uint32_t i = ids[t];
+        double acc[3] = {0.0, 0.0, 0.0}, acc2 = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == (int64_t)i) continue;
+            double dx[3], kv[3];
+            for (int k = 0; k < d; ++k) dx[k] = x[(int64_t)i * d + k] - x[j * d + k];
+            ora_pair_kernel(prm->kernel, d, prm->kparam, dx, kv);
+            for (int k = 0; k < d; ++k) {
+                acc[k] += kv[k];
+                acc2 += kv[k] * kv[k];
+            }
+        }
+        for (int k = 0; k < d; ++k) f[t * d + k] = acc[k] / (double)(n - 1);
+        m2[t] = acc2 / (double)(n - 1);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Time stepping                                                            */
 /* ------------------------------------------------------------------------ */

@@ -26,7 +26,7 @@ SYMBOLS = (
     "rbm_forces", "rbm_step_index", "rbm_check", "rbm_timing", "rbm_phase_times", "rbm_destroy",
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
     "cv_init", "cv_set_weights", "cv_get_weights", "cv_features", "cv_grads", "cv_train",
-    "rbm_force_sqerr", "ensemble_workspace_size", "ensemble_run",
+    "rbm_force_sqerr", "ensemble_workspace_size", "ensemble_run", "direct_moments",
 )
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
@@ -85,6 +85,7 @@ def lib():
         "rbm_phase_times": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "rbm_destroy": [vp],
         "direct_forces": [pp, vp, vp, i64, vp, vp],
+        "direct_moments": [pp, vp, vp, i64, vp, vp, vp],
         "direct_step": [pp, vp, vp, i64, vp],
         "cv_init": [vp, ctypes.c_uint64, vp],
         "cv_set_weights": [vp, vp, vp],
@@ -259,6 +260,20 @@ def direct_forces(prm: Params, x, ids=None, out=None, stream=None):
     _check(lib().direct_forces(ctypes.byref(prm.c()), _ptr(x), _ptr(ids), nids, _ptr(out),
                                _stream(stream)))
     return out
+
+
+def direct_moments(prm: Params, x, ids=None, stream=None):
+    """(F [nids][d], m2 [nids]): exact forces and 1/(N-1) sum_j |K(X_i - X_j)|^2."""
+    import torch
+    _expect(x, torch.float32, (prm.n, prm.d), "x")
+    nids = prm.n if ids is None else ids.numel()
+    if ids is not None:
+        _expect(ids, torch.int32, (nids,), "ids")
+    f = torch.empty((nids, prm.d), dtype=torch.float32, device=x.device)
+    m2 = torch.empty(nids, dtype=torch.float32, device=x.device)
+    _check(lib().direct_moments(ctypes.byref(prm.c()), _ptr(x), _ptr(ids), nids, _ptr(f), _ptr(m2),
+                                _stream(stream)))
+    return f, m2
 
 
 def direct_step(prm: Params, x, step: int, out=None, stream=None):

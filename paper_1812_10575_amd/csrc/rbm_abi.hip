@@ -552,6 +552,23 @@ rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_forces launch");
 }
 
+rbm_status direct_moments(const rbm_params *prm, const float *d_x, const uint32_t *d_ids, int64_t nids,
+                          float *d_f, float *d_m2, void *stream)
+{
+    rbm_status st = check_params(prm);
+    if (st == RBM_ERR_UNSUPPORTED && prm && prm->n <= RBM_MAX_N) st = RBM_OK;  // p is not used
+    if (st != RBM_OK) return st;
+    if (!d_x || !d_f || !d_m2) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (d_ids == nullptr) nids = prm->n;
+    if (nids < 0 || nids > prm->n) return fail(RBM_ERR_INVALID, "nids out of range");
+    if (nids == 0) return RBM_OK;
+    const Plan pl = make_plan(prm);
+    const StepArgs s = make_args(prm, pl, 0, false);
+    hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, d_ids, (uint32_t)nids, d_f, 0,
+                                      (hipStream_t)stream, d_m2);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_moments launch");
+}
+
 rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out, int64_t step,
                        void *stream)
 {

@@ -784,10 +784,16 @@ __global__ __launch_bounds__(1024) void k_sqerr(const float *__restrict__ f,
 // direct sum: F_i = 1/(N-1) sum_{j != i} K(X_i - X_j), LDS tiles of j, FP32
 // pair terms summed per tile, FP64 across tiles.  step: apply the update.
 // ---------------------------------------------------------------------------
-template <int D, int KERN, int TPB>
+// SELF: the pair j = i must be masked out (its scale can be infinite, a = 0
+// with a singular kernel).  Otherwise its term is exactly zero (dx = 0 and a
+// finite scale) and the mask is left out of the loop.
+// m2 != nullptr (force mode only): also m2[t] = 1/(N-1) sum_{j != i}
+// |K(X_i - X_j)|^2, the second moment behind the variance of Lemma 3.1.
+template <int D, int KERN, int TPB, bool SELF>
 __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restrict__ x,
                                                 const uint32_t *__restrict__ ids, uint32_t nids,
-                                                float *__restrict__ out, int step)
+                                                float *__restrict__ out, int step,
+                                                float *__restrict__ m2)
 {
     __shared__ float tile[TPB * D];
     const uint32_t t = blockIdx.x * TPB + threadIdx.x;
@@ -798,7 +804,7 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
     float xi[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) xi[c] = x[(size_t)i * D + c];
-    double acc[D];
+    double acc[D], acc2 = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0.0;
     for (uint32_t base = 0; base < s.n; base += TPB) {
@@ -810,9 +816,26 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
         }
         __syncthreads();
         const uint32_t cntj = min((uint32_t)TPB, s.n - base);
-        float part[D];
+        float part[D], part2 = 0.0f;
 #pragma unroll
         for (int c = 0; c < D; ++c) part[c] = 0.0f;
+        if (m2) {
+            for (uint32_t jj = 0; jj < cntj; ++jj) {
+                float dx[D];
+                float r2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    dx[c] = xi[c] - tile[jj * D + c];
+                    r2 = fmaf(dx[c], dx[c], r2);
+                }
+                float sc = pair_scale<KERN>(r2, s.a);
+                if constexpr (SELF) sc = (base + jj == i) ? 0.0f : sc;
+#pragma unroll
+                for (int c = 0; c < D; ++c) part[c] = fmaf(sc, dx[c], part[c]);
+                part2 = fmaf(sc * sc, r2, part2);
+            }
+            acc2 += (double)part2;
+        } else
         for (uint32_t jj = 0; jj < cntj; ++jj) {
             float dx[D];
             float r2 = 0.0f;
@@ -822,7 +845,7 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
                 r2 = fmaf(dx[c], dx[c], r2);
             }
             float sc = pair_scale<KERN>(r2, s.a);
-            sc = (base + jj == i) ? 0.0f : sc;
+            if constexpr (SELF) sc = (base + jj == i) ? 0.0f : sc;
 #pragma unroll
             for (int c = 0; c < D; ++c) part[c] = fmaf(sc, dx[c], part[c]);
         }
@@ -837,6 +860,7 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
     if (!step) {
 #pragma unroll
         for (int c = 0; c < D; ++c) out[(size_t)t * D + c] = f[c];
+        if (m2) m2[t] = valid ? (float)(acc2 * inv) : __builtin_nanf("");
     } else {
         em_update<D>(s, xi, f, i);
 #pragma unroll
@@ -1031,21 +1055,26 @@ hipError_t step_d(const Plan &pl, const StepArgs &s, int kernel, void *ws, hipSt
 
 template <int D, int KERN>
 hipError_t direct_dk(const StepArgs &s, const float *x, const uint32_t *ids, uint32_t nids,
-                     float *out, int step, hipStream_t st)
+                     float *out, int step, float *m2, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_direct<D, KERN, DIRECT_TPB>), dim3((nids + DIRECT_TPB - 1) / DIRECT_TPB),
-                       dim3(DIRECT_TPB), 0, st, s, x, ids, nids, out, step);
+    const dim3 g((nids + DIRECT_TPB - 1) / DIRECT_TPB);
+    if (KERN == K_GAUSS || s.a > 0.0f)
+        hipLaunchKernelGGL((k_direct<D, KERN, DIRECT_TPB, false>), g, dim3(DIRECT_TPB), 0, st, s, x, ids, nids,
+                           out, step, m2);
+    else
+        hipLaunchKernelGGL((k_direct<D, KERN, DIRECT_TPB, true>), g, dim3(DIRECT_TPB), 0, st, s, x, ids, nids,
+                           out, step, m2);
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t direct_d(const StepArgs &s, int kernel, const float *x, const uint32_t *ids,
-                    uint32_t nids, float *out, int step, hipStream_t st)
+                    uint32_t nids, float *out, int step, float *m2, hipStream_t st)
 {
     switch (kernel) {
-    case K_GAUSS: return direct_dk<D, K_GAUSS>(s, x, ids, nids, out, step, st);
-    case K_SOFTCOULOMB: return direct_dk<D, K_SOFTCOULOMB>(s, x, ids, nids, out, step, st);
-    default: return direct_dk<D, K_ATTREP>(s, x, ids, nids, out, step, st);
+    case K_GAUSS: return direct_dk<D, K_GAUSS>(s, x, ids, nids, out, step, m2, st);
+    case K_SOFTCOULOMB: return direct_dk<D, K_SOFTCOULOMB>(s, x, ids, nids, out, step, m2, st);
+    default: return direct_dk<D, K_ATTREP>(s, x, ids, nids, out, step, m2, st);
     }
 }
 
@@ -1103,12 +1132,12 @@ hipError_t launch_sqerr(const float *f, const uint32_t *ids, uint32_t nids, cons
 }
 
 hipError_t launch_direct(const StepArgs &s, int d, int kernel, const float *x, const uint32_t *ids,
-                         uint32_t nids, float *out, int step, hipStream_t st)
+                         uint32_t nids, float *out, int step, hipStream_t st, float *m2)
 {
     switch (d) {
-    case 1: return direct_d<1>(s, kernel, x, ids, nids, out, step, st);
-    case 2: return direct_d<2>(s, kernel, x, ids, nids, out, step, st);
-    default: return direct_d<3>(s, kernel, x, ids, nids, out, step, st);
+    case 1: return direct_d<1>(s, kernel, x, ids, nids, out, step, m2, st);
+    case 2: return direct_d<2>(s, kernel, x, ids, nids, out, step, m2, st);
+    default: return direct_d<3>(s, kernel, x, ids, nids, out, step, m2, st);
     }
 }
 

@@ -171,6 +171,47 @@ def test_direct_forces(name, n, nsample):
     assert np.max(np.abs(f - fo)) / scale <= 1e-5
 
 
+@pytest.mark.parametrize("name,n,nsample", [("gauss2d-n1024-p2", 3001, None),
+                                             ("dyson1d-n2^20-p2", 4000, None),
+                                             ("attrep3d-n2^24-p8", 1 << 20, 32)])
+def test_direct_moments(name, n, nsample):
+    """Forces and second moments of the direct sum against the oracle."""
+    w = rbm_inputs.params_of(name, n=n)
+    say("moments", name, n)
+    x = x0_of(w)
+    xt = torch.from_numpy(x).cuda()
+    ids = None if nsample is None else np.random.default_rng(1).choice(n, nsample, replace=False).astype(np.int32)
+    f, m2 = rbm.direct_moments(gp(w), xt, None if ids is None else torch.from_numpy(ids).cuda())
+    fo, m2o = ora.direct_moments(op(w), x.astype(np.float64), None if ids is None else ids.astype(np.uint32))
+    scale = max(1.0, float(np.max(np.abs(fo))))
+    assert np.max(np.abs(f.cpu().numpy() - fo)) / scale <= 1e-5
+    np.testing.assert_allclose(m2.cpu().numpy(), m2o, rtol=1e-5)
+
+
+@pytest.mark.parametrize("name,n,p", [("gauss2d-n1024-p2", 4096, 2), ("attrep3d-n2^24-p8", 8192, 8),
+                                      ("gauss2d-n1024-p2", 4096, 16)])
+def test_force_mse_follows_lemma_3_1(name, n, p):
+    """Over many divisions the mean squared RBM-1 force error equals
+    (1/(p-1) - 1/(N-1)) Lambda_i averaged over the particles, Lambda_i from
+    the direct sum's moments (Lemma 3.1; p divides N)."""
+    w = rbm_inputs.params_of(name, n=n, p=p)
+    say("lemma 3.1", name, n, p)
+    ctx, x0 = start(w)
+    x, _ = state(ctx)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    fd, m2 = rbm.direct_moments(gp(w), xt)
+    fd64 = fd.double()
+    lam = (n - 1) / (n - 2) * (m2.double() - (fd64 * fd64).sum(dim=1))
+    pred = float(((1.0 / (p - 1) - 1.0 / (n - 1)) * lam).mean())
+    acc, R = 0.0, 300
+    for m in range(R):
+        f = rbm.rbm_forces(ctx, 1000 + m).double()
+        acc += float(((f - fd64) ** 2).sum())
+    mse = acc / (R * n)
+    say("mse", mse, "predicted", pred)
+    assert abs(mse / pred - 1.0) < 0.03
+
+
 def test_full_size_attrep3d_step():
     """The headline size N = 2^24, p = 8: the whole permutation bit-exact and
     every particle within 1e-5 after one step, in the launch configuration

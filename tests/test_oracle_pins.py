@@ -244,6 +244,11 @@ def test_lemma_3_1_exactly(ora, n, p, kern, d):
             lam[i] = np.sum(np.sum((kij - kij.mean(axis=0)) ** 2, axis=1)) / (n - 2)
         pred = (1.0 / (p - 1) - 1.0 / (n - 1)) * lam
         np.testing.assert_allclose(var, pred, rtol=1e-11, atol=1e-14)
+        # the moment form of Lambda_i used at scale
+        fm, m2 = ora.direct_moments(prm, x)
+        np.testing.assert_allclose(fm, fd, rtol=1e-14, atol=1e-16)
+        lam2 = (n - 1) / (n - 2) * (m2 - np.sum(fd * fd, axis=1))
+        np.testing.assert_allclose((1.0 / (p - 1) - 1.0 / (n - 1)) * lam2, var, rtol=1e-10, atol=1e-14)
 
 
 def test_single_batch_is_the_direct_sum(ora):
