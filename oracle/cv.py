@@ -220,6 +220,37 @@ def cv_forces(theta_a, theta_c, x, perm, p, kfun=pair_kernel_gauss, use_bf16=Fal
     return f
 
 
+def cv_forces_ids(theta_a, theta_c, x, perm, p, ids, kfun=pair_kernel_gauss, use_bf16=False,
+                  chunk=1 << 18):
+    """cv_forces for the listed ids only, by the same definitions; the sum S
+    of c over all particles is taken in chunks so that large N fit in
+    memory."""
+    x = np.asarray(x, np.float64)
+    perm = np.asarray(perm, np.int64)
+    n = x.shape[0]
+    S = np.zeros((DIM, RANK))
+    for s0 in range(0, n, chunk):
+        S += features(theta_c, x[s0:s0 + chunk], use_bf16).sum(axis=0)
+    rank = np.empty(n, np.int64)
+    rank[perm] = np.arange(n)
+    nb = n // p
+    out = np.zeros((len(ids), DIM))
+    for t, i in enumerate(np.asarray(ids, np.int64)):
+        q = min(rank[i] // p, nb - 1)
+        bs = q * p
+        mates = perm[bs:(n if q == nb - 1 else bs + p)]
+        a = features(theta_a, x[[i]], use_bf16)[0]
+        c = features(theta_c, x[mates], use_bf16)
+        ci = features(theta_c, x[[i]], use_bf16)[0]
+        f = np.einsum("kr,kr->k", a, S - ci) / (n - 1)
+        res = np.zeros(DIM)
+        for jj, j in enumerate(mates):
+            if j != i:
+                res += kfun((x[i] - x[j])[None])[0] - np.einsum("kr,kr->k", a, c[jj])
+        out[t] = f + res / (len(mates) - 1)
+    return out
+
+
 def cv_step(theta_a, theta_c, prm, p, m, x, slots, kfun=pair_kernel_gauss, use_bf16=False):
     """One RBM-1 step with the control-variate force (division and noise as
     in the plain step of rbm_oracle.c).  Returns (x_new, slots_new)."""

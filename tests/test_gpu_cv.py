@@ -151,6 +151,27 @@ def test_cv_forces_match_oracle(n, p):
         assert math.sqrt(np.mean(err ** 2)) < 3e-4
 
 
+def test_cv_forces_at_full_size():
+    """The control-variate workload's size, N = 2^22, p = 2: forces of 64
+    sampled particles against the oracle (S over all particles in FP64)."""
+    w = rbm_inputs.params_of("gauss2d-n2^22-p2")
+    n, p = w["n"], w["p"]
+    ta, tc = thetas(23)
+    ctx, x0 = ctx_with(w, ta, tc)
+    rbm.rbm_run(ctx, 2)
+    x = rbm.rbm_positions(ctx).cpu().numpy()
+    s = rbm.rbm_perm(ctx).cpu().numpy().view(np.uint32)
+    f = rbm.rbm_forces(ctx, 2).cpu().numpy()
+    perm = ora.permutation(op(w), 2, s)
+    ids = np.random.default_rng(4).choice(n, 64, replace=False)
+    fo = cv.cv_forces_ids(ta, tc, x.astype(np.float64), perm, p, ids, use_bf16=True)
+    scale = max(1.0, float(np.max(np.abs(fo))))
+    err = np.abs(f[ids] - fo) / scale
+    say("full size cv force max err", err.max())
+    assert err.max() < 5e-3
+    assert math.sqrt(np.mean(err ** 2)) < 3e-4
+
+
 def test_cv_step_matches_oracle():
     w = wl(n=3000, p=2)
     ta, tc = thetas(17)

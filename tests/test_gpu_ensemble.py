@@ -177,3 +177,30 @@ def test_autotuner_picks_a_valid_tile(tmp_path):
     assert tile in list(autotune.candidates(ens))
     assert autotune.tune(ens, x, cache=cache) == tile  # from the cache
     assert np.array_equal(run(ens, x_before.cpu().numpy(), 0, 3, **tile), run(ens, x_before.cpu().numpy(), 0, 3))
+
+
+def test_full_ensemble_workload_sampled_systems():
+    """The ensemble workload itself (4096 systems, N_s log-uniform on [64,
+    65536], 500 steps, one graph-replayed launch with the autotuned tile):
+    sampled systems equal their standalone GPU runs bit for bit, and the
+    smallest ones stay within 2e-3 of the oracle after 500 steps."""
+    from paper_1812_10575_amd import autotune
+    E = rbm_inputs.ENSEMBLE
+    n, keys, x0 = rbm_inputs.ensemble()
+    ens = rbm.Ensemble(d=E["d"], kernel=E["kernel"], p=E["p"], sizes=n, seeds=keys, kparam=E["kparam"],
+                       beta=E["beta"], sigma=E["sigma"], dt=E["dt"])
+    x = torch.from_numpy(x0).cuda()
+    tile = autotune.tune(ens, x)
+    say("tile", tile)
+    rbm.ensemble_run(ens, x, 0, E["steps"], graph=True, **tile)
+    xe = x.cpu().numpy()
+    o = ens.offsets
+    order = np.argsort(n, kind="stable")
+    picks = [order[0], order[1], order[len(n) // 4], order[len(n) // 2], order[-len(n) // 4], order[-1]]
+    for s in picks:
+        say("system", s, "N", n[s])
+        assert np.array_equal(xe[o[s]:o[s + 1]], standalone(ens, s, x0, 0, E["steps"])), s
+    for s in picks[:2]:
+        err = ora.rel_max_error(xe[o[s]:o[s + 1]], oracle_run(ens, s, x0, 0, E["steps"]))
+        say("oracle e500", s, err)
+        assert err <= 2e-3

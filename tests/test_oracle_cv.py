@@ -190,3 +190,16 @@ def test_forward_of_a_hand_built_network():
                                atol=1e-13)
     # the feature layout: output 7 is component k = 0, rank r = 7
     assert np.array_equal(cv.features(th, x)[:, 0, 7], out[:, 7])
+
+
+def test_forces_for_listed_ids_agree_with_all_forces(thetas):
+    ta, tc = thetas
+    import oracle as ora
+    n, p = 203, 4
+    x = rbm_inputs.normal(n, 2, seed=21).astype(np.float64)
+    prm = ora.Params(d=2, kernel=ora.K_GAUSS, kparam=0.0, beta=1.0, sigma=0.0, dt=1e-3)
+    perm = ora.permutation(prm, 5, np.arange(n))
+    ids = [0, 7, 100, int(perm[-1]), int(perm[-5])]  # the last batch has p + 3 members
+    full = cv.cv_forces(ta, tc, x, perm, p, use_bf16=True)
+    np.testing.assert_allclose(cv.cv_forces_ids(ta, tc, x, perm, p, ids, use_bf16=True, chunk=50), full[ids],
+                               rtol=1e-12, atol=1e-14)
