@@ -94,6 +94,7 @@ rbm_status check_params(const rbm_params *prm)
 Plan make_plan(const rbm_params *prm)
 {
     Plan pl{};
+    pl.kb = 1;
     pl.n = (uint32_t)prm->n;
     pl.p = (uint32_t)prm->p;
     pl.nbat = pl.n / pl.p;
@@ -139,12 +140,13 @@ Plan make_plan(const rbm_params *prm)
             pl.off_stage2 = take(recs);
             pl.off_w2 = take((size_t)pl.n * 4);
         }
-        pl.off_kcnt = take((size_t)pl.ntf * pl.nbuck * 4);
-        pl.off_ftot = take((size_t)pl.nbuck * 4);
-        pl.off_fstart = take((size_t)(pl.nbuck + 1) * 4);
-        pl.off_fcur = take((size_t)pl.nbuck * 4);
-        pl.off_cstart = take((size_t)(pl.nb1 + 1) * 4);
-        pl.off_ccur = take((size_t)pl.nb1 * 4);
+        pl.kb = RBM_KEY_SETS;
+        pl.off_kcnt = take((size_t)pl.kb * pl.ntf * pl.nbuck * 4);
+        pl.off_ftot = take((size_t)pl.kb * pl.nbuck * 4);
+        pl.off_fstart = take((size_t)pl.kb * (pl.nbuck + 1) * 4);
+        pl.off_fcur = take((size_t)pl.kb * pl.nbuck * 4);
+        pl.off_cstart = take((size_t)pl.kb * (pl.nb1 + 1) * 4);
+        pl.off_ccur = take((size_t)pl.kb * pl.nb1 * 4);
     }
     pl.cv = prm->cv;
     if (pl.cv) {
@@ -294,13 +296,25 @@ rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
     if (ctx->m + nsteps > 0x100000000LL) return fail(RBM_ERR_INVALID, "step index would pass 2^32");
     const Plan &pl = ctx->plan;
     void *state = (char *)ctx->ws + pl.off_state;
+    const hipStream_t hs = (hipStream_t)stream;
+    uint32_t set = 0, group = 0;
     for (int64_t k = 0; k < nsteps; ++k) {
         const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)ctx->m, ctx->pending);
         hipEvent_t *ev = nullptr;
         if (ctx->trec < ctx->tmax) ev = ctx->ev + (size_t)ctx->trec++ * (RBM_NPHASES + 1);
-        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, (hipStream_t)stream, state,
-                                        nullptr, ev);
+        if (set == group) {
+            // the key passes of the next group of steps, in one launch each
+            group = (uint32_t)std::min<int64_t>(pl.kb, nsteps - k);
+            set = 0;
+            hipError_t e = rbm::launch_keys(pl, s, group, ctx->ws, hs, ev);
+            if (e != hipSuccess) return hip_fail(e, "rbm_step key launch");
+        } else if (ev) {
+            // this step's share of the key passes was timed with the group's first step
+            for (int i = 0; i < 4; ++i) (void)hipEventRecord(ev[i], hs);
+        }
+        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, ev, set, true);
         if (e != hipSuccess) return hip_fail(e, "rbm_step launch");
+        ++set;
         ctx->m += 1;
         ctx->pending = s.ssd != 0.0f;
     }

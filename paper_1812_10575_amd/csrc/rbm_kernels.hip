@@ -128,6 +128,8 @@ __global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, 
 {
     extern __shared__ uint32_t hist[];
     const uint32_t nb = s.nbuck;
+    s.m += blockIdx.y;  // key set y holds step m + y
+    cnt += (size_t)blockIdx.y * gridDim.x * nb;
     for (uint32_t i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * tilef;
@@ -151,6 +153,8 @@ __global__ __launch_bounds__(256) void k_key_colsum(uint32_t ntf, uint32_t nbuck
 {
     const uint32_t f = blockIdx.x * 256 + threadIdx.x;
     if (f >= nbuck) return;
+    cnt += (size_t)blockIdx.y * ntf * nbuck;  // key set y
+    ftot += (size_t)blockIdx.y * nbuck;
     uint32_t sum = 0;
     uint32_t t = 0;
     for (; t + 8 <= ntf; t += 8) {
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(256) void k_key_colsum(uint32_t ntf, uint32_t nbuck
     ftot[f] = sum;
 }
 
-// One workgroup: fine starts (fstart[nbuck] = N), coarse starts
+// One workgroup per key set: fine starts (fstart[nbuck] = N), coarse starts
 // cstart[c] = fstart[c << shift], and the run cursors of both levels.
 // Global memory is read and written in coalesced order through LDS; thread t
 // scans the PER consecutive totals it owns (the LDS index is padded by one
@@ -186,6 +190,12 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
     __shared__ uint32_t tmp[TPB / 64];
     auto pad = [](uint32_t i) { return i + (i >> 5); };
     const uint32_t t = threadIdx.x;
+    // workgroup k: key set k
+    ftot += (size_t)blockIdx.x * nbuck;
+    fstart += (size_t)blockIdx.x * (nbuck + 1);
+    fcur += (size_t)blockIdx.x * nbuck;
+    cstart += (size_t)blockIdx.x * (nb1 + 1);
+    ccur += (size_t)blockIdx.x * nb1;
     bool over = false;
     for (uint32_t i = t; i < (uint32_t)RBM_MAX_FINE; i += TPB) {
         const uint32_t v = i < nbuck ? ftot[i] : 0u;
@@ -895,8 +905,48 @@ T *at(void *ws, size_t off)
 // Control-variate step (d = 2, Gaussian kernel): S = sum_j c(X_j) in FP64,
 // the same division as the plain step with the records written in rank
 // order, then the control-variate batch force and the drift update.
+// Buffers of key set k.
+struct KeySet {
+    uint32_t *kcnt, *ftot, *fstart, *fcur, *cstart, *ccur;
+};
+
+KeySet key_set(const Plan &pl, void *ws, uint32_t k)
+{
+    KeySet q;
+    q.kcnt = at<uint32_t>(ws, pl.off_kcnt) + (size_t)k * pl.ntf * pl.nbuck;
+    q.ftot = at<uint32_t>(ws, pl.off_ftot) + (size_t)k * pl.nbuck;
+    q.fstart = at<uint32_t>(ws, pl.off_fstart) + (size_t)k * (pl.nbuck + 1);
+    q.fcur = at<uint32_t>(ws, pl.off_fcur) + (size_t)k * pl.nbuck;
+    q.cstart = at<uint32_t>(ws, pl.off_cstart) + (size_t)k * (pl.nb1 + 1);
+    q.ccur = at<uint32_t>(ws, pl.off_ccur) + (size_t)k * pl.nb1;
+    return q;
+}
+
+hipError_t keys_impl(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
+                     hipEvent_t *ev)
+{
+    mark(ev, 0, st);
+    if (pl.nbuck > 1) {
+        const KeySet q = key_set(pl, ws, 0);
+        auto *flags = at<uint32_t>(ws, pl.off_flags);
+        hipLaunchKernelGGL(k_key_count, dim3(pl.ntf, count), dim3(1024), (size_t)pl.nbuck * 4, st, s, pl.tilef,
+                           q.kcnt);
+        mark(ev, 1, st);
+        hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256, count), dim3(256), 0, st, pl.ntf,
+                           pl.nbuck, q.kcnt, q.ftot);
+        mark(ev, 2, st);
+        hipLaunchKernelGGL(k_key_starts, dim3(count), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
+                           (uint32_t)SORT_CAP, q.ftot, q.fstart, q.fcur, q.cstart, q.ccur, flags);
+    } else {
+        mark(ev, 1, st);
+        mark(ev, 2, st);
+    }
+    mark(ev, 3, st);
+    return hipGetLastError();
+}
+
 hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, void *dst_state,
-                   float *fout, hipEvent_t *ev)
+                   float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready)
 {
     auto *state = at<Rec<2>>(ws, pl.off_state);
     auto *sorted = at<Rec<2>>(ws, pl.off_sorted);
@@ -904,31 +954,24 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     const float *master = at<float>(ws, pl.off_cvmaster);
     const __bf16 *wb = at<__bf16>(ws, pl.off_cvwb);
     double *S = at<double>(ws, pl.off_cvS);
-    mark(ev, 0, st);
+    if (!keys_ready) {
+        hipError_t e = keys_impl(pl, s, 1, ws, st, ev);
+        if (e != hipSuccess) return e;
+        set = 0;
+    }
+    // phase A (c of every particle, S) is timed with the scatter
     hipError_t e = cv_launch_csum(s, state, master, wb, at<double>(ws, pl.off_cvspart), S, st);
     if (e != hipSuccess) return e;
     if (pl.nbuck == 1) {
-        for (int i = 1; i <= 5; ++i) mark(ev, i, st);
+        for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
                            dim3(1), dim3(SINGLE_TPB), 0, st, s, state, nullptr, nullptr, sorted,
                            nullptr, flags);
     } else {
         auto *stage1 = at<Rec<2>>(ws, pl.off_stage1);
         auto *w1 = at<uint32_t>(ws, pl.off_w1);
-        auto *fstart = at<uint32_t>(ws, pl.off_fstart);
-        auto *fcur = at<uint32_t>(ws, pl.off_fcur);
-        auto *cstart = at<uint32_t>(ws, pl.off_cstart);
-        auto *ccur = at<uint32_t>(ws, pl.off_ccur);
-        hipLaunchKernelGGL(k_key_count, dim3(pl.ntf), dim3(1024), (size_t)pl.nbuck * 4, st, s,
-                           pl.tilef, at<uint32_t>(ws, pl.off_kcnt));
-        mark(ev, 1, st);
-        hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256), dim3(256), 0, st, pl.ntf,
-                           pl.nbuck, at<uint32_t>(ws, pl.off_kcnt), at<uint32_t>(ws, pl.off_ftot));
-        mark(ev, 2, st);
-        hipLaunchKernelGGL(k_key_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift,
-                           pl.n, (uint32_t)SORT_CAP, at<uint32_t>(ws, pl.off_ftot), fstart, fcur,
-                           cstart, ccur, flags);
-        mark(ev, 3, st);
+        const KeySet q = key_set(pl, ws, set);
+        uint32_t *fstart = q.fstart, *fcur = q.fcur, *cstart = q.cstart, *ccur = q.ccur;
         const Rec<2> *src = stage1;
         const uint32_t *wsrc = w1;
         if (pl.shift > 0) {
@@ -979,16 +1022,21 @@ void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const
 
 template <int D, int KERN>
 hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, void *dst_state,
-                   float *fout, hipEvent_t *ev)
+                   float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready)
 {
     auto *state = at<Rec<D>>(ws, pl.off_state);
     auto *dst = reinterpret_cast<Rec<D> *>(dst_state);
     auto *flags = at<uint32_t>(ws, pl.off_flags);
     if constexpr (D == 2 && KERN == K_GAUSS) {
-        if (pl.cv) return step_cv(pl, s, ws, st, dst_state, fout, ev);
+        if (pl.cv) return step_cv(pl, s, ws, st, dst_state, fout, ev, set, keys_ready);
+    }
+    if (!keys_ready) {
+        hipError_t e = keys_impl(pl, s, 1, ws, st, ev);
+        if (e != hipSuccess) return e;
+        set = 0;
     }
     if (pl.nbuck == 1) {
-        for (int i = 0; i <= 5; ++i) mark(ev, i, st);
+        for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         launch_sort<D, KERN, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS>(
             pl.p, dim3(1), st, s, state, nullptr, nullptr, dst, fout, flags);
         mark(ev, 6, st);
@@ -997,23 +1045,9 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     }
     auto *stage1 = at<Rec<D>>(ws, pl.off_stage1);
     auto *w1 = at<uint32_t>(ws, pl.off_w1);
-    auto *kcnt = at<uint32_t>(ws, pl.off_kcnt);
-    auto *ftot = at<uint32_t>(ws, pl.off_ftot);
-    auto *fstart = at<uint32_t>(ws, pl.off_fstart);
-    auto *fcur = at<uint32_t>(ws, pl.off_fcur);
-    auto *cstart = at<uint32_t>(ws, pl.off_cstart);
-    auto *ccur = at<uint32_t>(ws, pl.off_ccur);
+    const KeySet q = key_set(pl, ws, set);
+    uint32_t *fstart = q.fstart, *fcur = q.fcur, *cstart = q.cstart, *ccur = q.ccur;
     const bool split = pl.shift > 0;
-    mark(ev, 0, st);
-    hipLaunchKernelGGL(k_key_count, dim3(pl.ntf), dim3(1024), (size_t)pl.nbuck * 4, st, s, pl.tilef,
-                       kcnt);
-    mark(ev, 1, st);
-    hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256), dim3(256), 0, st, pl.ntf,
-                       pl.nbuck, kcnt, ftot);
-    mark(ev, 2, st);
-    hipLaunchKernelGGL(k_key_starts, dim3(1), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
-                       (uint32_t)SORT_CAP, ftot, fstart, fcur, cstart, ccur, flags);
-    mark(ev, 3, st);
     const Rec<D> *src = stage1;
     const uint32_t *wsrc = w1;
     if (split) {
@@ -1044,12 +1078,12 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
 
 template <int D>
 hipError_t step_d(const Plan &pl, const StepArgs &s, int kernel, void *ws, hipStream_t st,
-                  void *dst, float *fout, hipEvent_t *ev)
+                  void *dst, float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready)
 {
     switch (kernel) {
-    case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev);
-    case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev);
-    default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev);
+    case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     }
 }
 
@@ -1080,13 +1114,22 @@ hipError_t direct_d(const StepArgs &s, int kernel, const float *x, const uint32_
 
 }  // namespace
 
-hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
-                       hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev)
+hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
+                       hipEvent_t *ev)
 {
+    if (count < 1 || count > pl.kb) return hipErrorInvalidValue;
+    return keys_impl(pl, s, count, ws, st, ev);
+}
+
+hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
+                       hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set,
+                       bool keys_ready)
+{
+    if (keys_ready && set >= pl.kb) return hipErrorInvalidValue;
     switch (d) {
-    case 1: return step_d<1>(pl, s, kernel, ws, st, dst_state, fout, ev);
-    case 2: return step_d<2>(pl, s, kernel, ws, st, dst_state, fout, ev);
-    default: return step_d<3>(pl, s, kernel, ws, st, dst_state, fout, ev);
+    case 1: return step_d<1>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
+    case 2: return step_d<2>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
+    default: return step_d<3>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
     }
 }
 

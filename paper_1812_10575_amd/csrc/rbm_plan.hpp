@@ -16,6 +16,7 @@
 // four workgroups share a CU.
 #define RBM_BUCKET_MEAN 1024
 #define RBM_SORT_CAP 1520
+#define RBM_KEY_SETS 8
 #define RBM_MAX_FINE 32768
 #define RBM_LVL_TPB 512
 #define RBM_TILE (16 * RBM_LVL_TPB)
@@ -37,6 +38,7 @@ struct Plan {
     uint32_t ntiles;  // coarse-scatter tiles of RBM_TILE slots
     uint32_t tilef;   // slots per key-count tile
     uint32_t ntf;     // key-count tiles
+    uint32_t kb;      // key sets: the key passes of up to kb consecutive steps run as one launch
     size_t rec_bytes;
     size_t off_state, off_scratch, off_stage1, off_w1, off_stage2, off_w2;
     size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;
@@ -47,8 +49,16 @@ struct Plan {
     size_t total;
 };
 
+// Key passes (bucket counts, totals, starts and run cursors) of steps s.m ..
+// s.m + count - 1 into key sets 0 .. count - 1 (count <= pl.kb).  ev: the
+// first four phase events of the step that starts the group (may be null).
+hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
+                       hipEvent_t *ev);
+// One step with the keys of key set `set`; keys_ready == false computes
+// them first (into that set).
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
-                       hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev);
+                       hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set = 0,
+                       bool keys_ready = false);
 hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *slots, void *ws,
                        hipStream_t st);
 // x != NULL: positions by id, with the pending noise of s added.
