@@ -307,10 +307,11 @@ __device__ __forceinline__ void fwd_tile(const NetLds &N, float x0, float x1, __
     __builtin_amdgcn_wave_barrier();
 }
 
-// Partial sums of c(X_j) over the state records (slot order, pending noise
-// added): part[wg][32] in FP64.  Workgroup wg takes tiles of 256 records wg,
-// wg + G, ...; each lane sums its samples in tile order, then the lanes and
-// waves of the workgroup are added in a fixed order.
+// Partial sums of c(X_j) over the records (pending noise of s added, if
+// any): part[wg][32] in FP64, and c itself to cout[j][32] (FP32) when cout is
+// not null.  Workgroup wg takes tiles of 256 records wg, wg + G, ...; each
+// lane sums its samples in tile order, then the lanes and waves of the
+// workgroup are added in a fixed order.
 struct SumLds {
     NetLds net;
     float X[256][2];
@@ -321,7 +322,7 @@ struct SumLds {
 __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restrict__ state,
                                               const float *__restrict__ master,
                                               const __bf16 *__restrict__ wb,
-                                              double *__restrict__ part)
+                                              double *__restrict__ part, float *__restrict__ cout)
 {
     __shared__ SumLds L;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
@@ -347,11 +348,17 @@ __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restri
             float out[2][4];
             fwd_tile(L.net, L.X[m + col][0], L.X[m + col][1], L.H2[w], out);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (base + m + 4 * g + i < s.n) {
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t r = base + m + 4 * g + i;
+                if (r < s.n) {
                     acc[0] += (double)out[0][i];
                     acc[1] += (double)out[1][i];
+                    if (cout) {
+                        cout[(size_t)r * CV_NO + col] = out[0][i];
+                        cout[(size_t)r * CV_NO + 16 + col] = out[1][i];
+                    }
                 }
+            }
         }
         __syncthreads();
     }
@@ -390,9 +397,10 @@ __global__ __launch_bounds__(1024) void k_csum_final(uint32_t nwg, const double 
 // Tile b < T-1 holds batches [b qb, min((b+1) qb, nbat-1)); tile T-1 holds
 // the last batch (p plus the leftover ranks).  qb = 128 / p, so a tile has at
 // most CV_MAXR = 128 records (p <= 64).  Persistent workgroups take tiles b,
-// b + G, ... with both nets staged in LDS once.
+// b + G, ... with net a staged in LDS once; c of every record comes from
+// k_csum, which ran over the same key-ordered records.
 struct BatchLds {
-    NetLds net[2];
+    NetLds net;  // a
     float X[CV_MAXR][2];
     uint32_t id[CV_MAXR];
     float A[CV_MAXR][CV_NO + 1];  // padded rows: one record per lane hits distinct banks
@@ -404,6 +412,7 @@ struct BatchLds {
 template <int KERN>
 __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint32_t ntiles,
                                                   const Rec<2> *__restrict__ sorted,
+                                                  const float *__restrict__ cin,
                                                   const float *__restrict__ master,
                                                   const __bf16 *__restrict__ wb,
                                                   const double *__restrict__ S,
@@ -411,8 +420,7 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
 {
     __shared__ BatchLds L;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
-    stage_net(L.net[0], master, wb, 0);
-    stage_net(L.net[1], master, wb, 1);
+    stage_net(L.net, master, wb, 0);
     if (tid < CV_NO) L.sn[tid] = (float)(S[tid] / (double)(s.n - 1));
     const float inv_n1 = 1.0f / (float)(s.n - 1);
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -428,6 +436,14 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
         const uint32_t r1 = (q1 == s.nbat) ? s.n : q1 * s.p;
         const uint32_t nr = r1 - r0;  // <= CV_MAXR by the tiling
         __syncthreads();              // the previous tile is done with the LDS
+        // c of the tile's records (computed with S by k_csum): loaded now,
+        // stored to LDS once a is computed, so the loads overlap that work
+        float cr[CV_MAXR * CV_NO / 256];
+#pragma unroll
+        for (int k = 0; k < CV_MAXR * CV_NO / 256; ++k) {
+            const uint32_t e = tid + 256 * k;
+            cr[k] = e < nr * CV_NO ? cin[(size_t)r0 * CV_NO + e] : 0.0f;
+        }
         if (tid < CV_MAXR) {
             float xy[2] = {0.0f, 0.0f};
             uint32_t id = 0;
@@ -442,20 +458,21 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
             L.id[tid] = id;
         }
         __syncthreads();
-        // a and c of the tile's records: wave w takes rows 32 w .. 32 w + 31
+        // a of the tile's records: wave w takes rows 32 w .. 32 w + 31
 #pragma unroll 1
-        for (int net = 0; net < 2; ++net) {
-            float(*dstf)[CV_NO + 1] = net == 0 ? L.A : L.C;
-#pragma unroll 1
-            for (int mt = 0; mt < 2; ++mt) {
-                const int m = 32 * w + 16 * mt;
-                float out[2][4];
-                fwd_tile(L.net[net], L.X[m + col][0], L.X[m + col][1], L.H2[w], out);
+        for (int mt = 0; mt < 2; ++mt) {
+            const int m = 32 * w + 16 * mt;
+            float out[2][4];
+            fwd_tile(L.net, L.X[m + col][0], L.X[m + col][1], L.H2[w], out);
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) dstf[m + 4 * g + i][16 * t + col] = out[t][i];
-            }
+                for (int i = 0; i < 4; ++i) L.A[m + 4 * g + i][16 * t + col] = out[t][i];
+        }
+#pragma unroll
+        for (int k = 0; k < CV_MAXR * CV_NO / 256; ++k) {
+            const uint32_t e = tid + 256 * k;
+            L.C[e / CV_NO][e % CV_NO] = cr[k];
         }
         __syncthreads();
         // forces, one thread per record
@@ -829,17 +846,18 @@ hipError_t cv_launch_features(const float *master, const __bf16 *wb, const float
 }
 
 hipError_t cv_launch_csum(const StepArgs &s, const void *state, const float *master,
-                          const __bf16 *wb, double *part, double *S, hipStream_t st)
+                          const __bf16 *wb, double *part, double *S, float *cout, hipStream_t st)
 {
     const uint32_t g = min((s.n + 255) / 256, (uint32_t)CV_SUM_WG);
     hipLaunchKernelGGL(cvk::k_csum, dim3(g), dim3(256), 0, st, s, (const Rec<2> *)state, master, wb,
-                       part);
+                       part, cout);
     hipLaunchKernelGGL(cvk::k_csum_final, dim3(1), dim3(1024), 0, st, g, part, S);
     return hipGetLastError();
 }
 
-hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const float *master,
-                           const __bf16 *wb, const double *S, void *dst, float *fout, hipStream_t st)
+hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const float *c,
+                           const float *master, const __bf16 *wb, const double *S, void *dst, float *fout,
+                           hipStream_t st)
 {
     const uint32_t qb = cv_batches_per_wg(s.p);
     const uint32_t ntiles = (s.nbat - 1 + qb - 1) / qb + 1;
@@ -856,7 +874,7 @@ hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, co
     }
     const uint32_t g = min(ntiles, (uint32_t)resident);
     hipLaunchKernelGGL(cvk::k_cv_batch<K_GAUSS>, dim3(g), dim3(256), 0, st, s, qb, ntiles,
-                       (const Rec<2> *)sorted, master, wb, S, (Rec<2> *)dst, fout);
+                       (const Rec<2> *)sorted, c, master, wb, S, (Rec<2> *)dst, fout);
     return hipGetLastError();
 }
 

@@ -959,9 +959,7 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         if (e != hipSuccess) return e;
         set = 0;
     }
-    // phase A (c of every particle, S) is timed with the scatter
-    hipError_t e = cv_launch_csum(s, state, master, wb, at<double>(ws, pl.off_cvspart), S, st);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     if (pl.nbuck == 1) {
         for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
@@ -994,8 +992,15 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
                            dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
                            nullptr, flags);
     }
+    // phase A over the key-ordered records (their noise is in): c of every
+    // particle, kept for phase B, and S; timed with the batch phase
     mark(ev, 6, st);
-    e = cv_launch_batch(s, K_GAUSS, sorted, master, wb, S, dst_state, fout, st);
+    StepArgs sa = s;
+    sa.pssd = 0.0f;
+    float *cbuf = at<float>(ws, pl.off_cvc);
+    e = cv_launch_csum(sa, sorted, master, wb, at<double>(ws, pl.off_cvspart), S, cbuf, st);
+    if (e != hipSuccess) return e;
+    e = cv_launch_batch(s, K_GAUSS, sorted, cbuf, master, wb, S, dst_state, fout, st);
     mark(ev, 7, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();

@@ -44,7 +44,7 @@ struct Plan {
     size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;
     // control variate (cv != 0)
     int cv;
-    size_t off_sorted, off_cvmaster, off_cvam, off_cvav, off_cvwb, off_cvspart, off_cvS;
+    size_t off_sorted, off_cvc, off_cvmaster, off_cvam, off_cvav, off_cvwb, off_cvspart, off_cvS;
     size_t off_cvgpart, off_cvlpart, off_cvgrad, off_cvloss;
     size_t total;
 };
