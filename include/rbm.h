@@ -220,15 +220,18 @@ typedef struct {
 /* Launch shape (the autotuner's search space); zeros select the defaults. */
 typedef struct {
     int32_t lds_max;  /* a system run by a whole workgroup stays in LDS up to
-                         this size (<= RBM_ENS_LDS; default RBM_ENS_LDS);
-                         larger ones are streamed */
-    int32_t grid;     /* persistent workgroups (default: one per compute unit) */
+                         this size (<= 4 wg; default 4 wg); larger ones are
+                         streamed */
+    int32_t grid;     /* persistent workgroups (default: as many as fit at once) */
     int32_t team;     /* threads per system for systems of at most 4 team
-                         particles, run 1024 / team to a workgroup: a power of
-                         two in 64..1024 (default 256; 1024: one system per
+                         particles, run wg / team to a workgroup: a power of
+                         two in 64..wg (default 256; wg: one system per
                          workgroup) */
-    int32_t bucket;   /* mean bucket of a streamed system, 256..3072 (default
-                         2048); at most 256 buckets per system */
+    int32_t bucket;   /* mean bucket of a streamed system, 256..3 wg / 4
+                         (default wg); at most 256 buckets per system */
+    int32_t wg;       /* threads per workgroup: 1024 (4096 records of LDS, one
+                         workgroup per compute unit) or 512 (2048 records, two);
+                         0: 1024 */
 } rbm_ensemble_tile;
 
 #define RBM_ENS_LDS 4096

@@ -55,7 +55,7 @@ class rbm_ensemble(ctypes.Structure):
 
 class rbm_ensemble_tile(ctypes.Structure):
     _fields_ = [("lds_max", ctypes.c_int32), ("grid", ctypes.c_int32), ("team", ctypes.c_int32),
-                ("bucket", ctypes.c_int32)]
+                ("bucket", ctypes.c_int32), ("wg", ctypes.c_int32)]
 
 
 _lib = None
@@ -398,7 +398,7 @@ def ensemble_workspace_size(ens: Ensemble) -> int:
 
 
 def ensemble_run(ens: Ensemble, x, step0: int, nsteps: int, lds_max: int = 0, grid: int = 0,
-                 team: int = 0, bucket: int = 0, graph: bool = True, ws=None, stream=None):
+                 team: int = 0, bucket: int = 0, wg: int = 0, graph: bool = True, ws=None, stream=None):
     """Runs steps step0 .. step0 + nsteps - 1 of every system in place on x
     [sum sizes][d] (FP32, system by system, each by particle id).  Returns
     when the launch has completed."""
@@ -409,7 +409,7 @@ def ensemble_run(ens: Ensemble, x, step0: int, nsteps: int, lds_max: int = 0, gr
     need = ensemble_workspace_size(ens)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
-    tile = rbm_ensemble_tile(lds_max, grid, team, bucket)
+    tile = rbm_ensemble_tile(lds_max, grid, team, bucket, wg)
     _check(lib().ensemble_run(ctypes.byref(ens.c()), n.ctypes.data_as(ctypes.c_void_p),
                               sd.ctypes.data_as(ctypes.c_void_p), _ptr(x), step0, nsteps, ctypes.byref(tile),
                               _ptr(ws), ws.numel(), 1 if graph else 0, _stream(stream)))

@@ -1,7 +1,8 @@
 """Launch-shape autotuner of the batched ensemble (ensemble_run).
 
-The tile of an ensemble launch has three knobs, each acting on one size
-class of systems:
+The tile of an ensemble launch has a workgroup shape (1024 threads with 4096
+records of LDS, or 512 threads with 2048 records and two workgroups per
+compute unit) and three knobs, each acting on one size class of systems:
   team    threads per system for systems of at most 4 team particles, which
           run 1024 / team to a workgroup;
   lds_max whole-workgroup systems up to this size stay in LDS for all steps;
@@ -21,9 +22,7 @@ import numpy as np
 
 from . import Ensemble, ensemble_run, ensemble_workspace_size
 
-TEAMS = (64, 128, 256, 512, 1024)
-BUCKETS = (1024, 2048, 3072)
-LDS_MAX = (2048, 4096)
+WGS = (1024, 512)  # threads per workgroup (4096 or 2048 records of LDS)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 
@@ -36,12 +35,15 @@ def key_of(ens: Ensemble, arch: str) -> str:
 
 def candidates(ens: Ensemble):
     nmax = int(np.max(ens.sizes))
-    for team in TEAMS:
-        for bucket in BUCKETS:
-            if (nmax + bucket - 1) // bucket > 256:
+    for wg in WGS:
+        for team in (64, 128, 256, 512, 1024):
+            if team > wg:
                 continue
-            for lds_max in LDS_MAX:
-                yield dict(team=team, bucket=bucket, lds_max=lds_max)
+            for bucket in (wg, 2 * wg, 3 * wg):
+                if (nmax + bucket - 1) // bucket > 256:
+                    continue
+                for lds_max in (2 * wg, 4 * wg):
+                    yield dict(wg=wg, team=team, bucket=bucket, lds_max=lds_max)
 
 
 def _arch():

@@ -685,14 +685,17 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     int grid = tile ? tile->grid : 0;
     int team = tile ? tile->team : 0;
     int bucket = tile ? tile->bucket : 0;
-    if (lds_max == 0) lds_max = RBM_ENS_LDS;
+    int wg = tile ? tile->wg : 0;
+    if (wg == 0) wg = 1024;
+    if (wg != 1024 && wg != 512) return fail(RBM_ERR_INVALID, "wg = %d is not 512 or 1024", wg);
+    if (lds_max == 0) lds_max = 4 * wg;
     if (team == 0) team = 256;
-    if (bucket == 0) bucket = 2048;
-    if (lds_max < 0 || lds_max > RBM_ENS_LDS) return fail(RBM_ERR_INVALID, "lds_max = %d not in 0..%d", lds_max, RBM_ENS_LDS);
+    if (bucket == 0) bucket = wg;
+    if (lds_max < 0 || lds_max > 4 * wg) return fail(RBM_ERR_INVALID, "lds_max = %d not in 0..%d", lds_max, 4 * wg);
     if (grid < 0 || grid > 65536) return fail(RBM_ERR_INVALID, "grid = %d not in 0..65536", grid);
-    if (team < 64 || team > 1024 || (team & (team - 1)) != 0)
-        return fail(RBM_ERR_INVALID, "team = %d is not a power of two in 64..1024", team);
-    if (bucket < 256 || bucket > 3072) return fail(RBM_ERR_INVALID, "bucket = %d not in 256..3072", bucket);
+    if (team < 64 || team > wg || (team & (team - 1)) != 0)
+        return fail(RBM_ERR_INVALID, "team = %d is not a power of two in 64..%d", team, wg);
+    if (bucket < 256 || bucket > 3 * wg) return fail(RBM_ERR_INVALID, "bucket = %d not in 256..%d", bucket, 3 * wg);
     int64_t nmax = 0;
     for (int64_t i = 0; i < e->nsys; ++i) nmax = std::max(nmax, h_n[i]);
     if (nmax > lds_max && (nmax + bucket - 1) / bucket > RBM_ENS_MAXB)
@@ -703,7 +706,7 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
         hipError_t he = hipGetDevice(&dev);
         if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (he != hipSuccess) return hip_fail(he, "compute unit count");
-        grid = cus;
+        grid = cus * (wg == 512 ? 2 : 1);
     }
     if (nsteps == 0) return RBM_OK;
     const hipStream_t hs = (hipStream_t)stream;
@@ -725,9 +728,9 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return sys[a].n > sys[b].n; });
     // work items in queue order: every system above 4 team particles alone,
-    // then the rest in groups of 1024 / team consecutive systems
+    // then the rest in groups of wg / team consecutive systems
     std::vector<uint32_t> items;  // pairs (first, count)
-    const uint32_t g = 1024u / (uint32_t)team, cap = 4u * (uint32_t)team;
+    const uint32_t g = (uint32_t)wg / (uint32_t)team, cap = 4u * (uint32_t)team;
     for (size_t i = 0; i < order.size();) {
         uint32_t c = 1;
         if (g > 1 && sys[order[i]].n <= cap) c = (uint32_t)std::min<size_t>(g, order.size() - i);
@@ -757,6 +760,7 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     L.nsteps = nsteps;
     L.nitems = nitems;
     L.lds_max = (uint32_t)lds_max;
+    L.wg = (uint32_t)wg;
     L.team = (uint32_t)team;
     L.bmean = (uint32_t)bucket;
     L.grid = (uint32_t)grid;

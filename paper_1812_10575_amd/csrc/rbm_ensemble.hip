@@ -30,24 +30,30 @@
 namespace rbm {
 namespace ens {
 
-constexpr int TPB = 1024;
-constexpr int CAP = RBM_ENS_LDS;  // records in LDS (all teams together)
-constexpr int S = CAP;            // sub-bucket counters (4 per thread)
-constexpr int E = CAP / TPB;      // records per thread
+// Two workgroup shapes: W = 1024 threads with 4096 records of LDS (one
+// workgroup per compute unit), or W = 512 with 2048 (two per compute unit).
+// In both, a thread owns E = 4 records and 4 sub-bucket counters.
+constexpr int E = 4;
 constexpr int MAXB = RBM_ENS_MAXB;
-constexpr int MAXG = TPB / 64;    // teams per workgroup at most
+#define RBM_ENS_SHAPE                                                                              \
+    constexpr int TPB = W;       /* threads */                                                     \
+    constexpr int CAP = 4 * W;   /* records in LDS, all teams together */                          \
+    constexpr int S = 4 * W;     /* sub-bucket counters */                                         \
+    (void)TPB;                                                                                     \
+    (void)CAP;                                                                                     \
+    (void)S
 
 using Sys = EnsSys;
 
-template <int D>
+template <int D, int W>
 struct Lds {
-    Rec<D> a[CAP];      // records (slot order / bucket input)
-    Rec<D> b[CAP];      // records in key order
-    uint32_t w[CAP];    // PERM words
-    uint16_t tmp[CAP];  // sub-bucket member lists
-    uint32_t cnt[S];    // sub-bucket counts, then starts (team slices of 4 T)
-    uint32_t tot[MAXG]; // records per team slice
-    uint32_t scan[TPB / 64];
+    Rec<D> a[4 * W];      // records (slot order / bucket input)
+    Rec<D> b[4 * W];      // records in key order
+    uint32_t w[4 * W];    // PERM words
+    uint16_t tmp[4 * W];  // sub-bucket member lists
+    uint32_t cnt[4 * W];  // sub-bucket counts, then starts (team slices of 4 T)
+    uint32_t tot[W / 64]; // records per team slice
+    uint32_t scan[W / 64];
     uint32_t hist[MAXB + 1];
     uint32_t cur[MAXB];
     uint32_t item;
@@ -89,8 +95,8 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan_e(uint32_t v)
 // Exclusive scan of every team's counter slice in place (thread tid owns
 // counters 4 tid .. 4 tid + 3, which lie in its team's slice); the team's
 // total goes to L.tot.  Ends with a barrier.
-template <int D>
-__device__ void scan_cnt(Lds<D> &L, const Team &tm)
+template <int D, int W>
+__device__ void scan_cnt(Lds<D, W> &L, const Team &tm)
 {
     const uint32_t tid = threadIdx.x;
     uint32_t v[4], sum = 0;
@@ -122,9 +128,10 @@ __device__ void scan_cnt(Lds<D> &L, const Team &tm)
 // Order the team's records a[0..cnt) (team-relative) by the key
 // (w << 32 | id), writing b[base_b + rank].  sub(w) is the sub-bucket of a
 // word, monotone in w, in [0, 4 T).  Ends with a barrier.
-template <int D, typename SubFn>
-__device__ void sort_into_b(Lds<D> &L, const Team &tm, uint32_t cnt, uint32_t base_b, SubFn sub)
+template <int D, int W, typename SubFn>
+__device__ void sort_into_b(Lds<D, W> &L, const Team &tm, uint32_t cnt, uint32_t base_b, SubFn sub)
 {
+    RBM_ENS_SHAPE;
     const uint32_t tid = threadIdx.x, R = tm.base;
     for (uint32_t i = tid; i < (uint32_t)S; i += TPB) L.cnt[i] = 0;
     __syncthreads();
@@ -138,7 +145,7 @@ __device__ void sort_into_b(Lds<D> &L, const Team &tm, uint32_t cnt, uint32_t ba
         }
     }
     __syncthreads();
-    scan_cnt<D>(L, tm);
+    scan_cnt<D, W>(L, tm);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tm.lt + k * tm.T;
@@ -266,8 +273,8 @@ __device__ __forceinline__ uint4 words4(const StepArgs &s, uint32_t k)
 
 // The team's system (n <= 4 T particles, n = 0 for an idle team) in LDS for
 // all steps.  Every team of the workgroup runs the same number of steps.
-template <int D, int KERN, int P>
-__device__ void run_small(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps, float *__restrict__ x)
+template <int D, int KERN, int P, int W>
+__device__ void run_small(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nsteps, float *__restrict__ x)
 {
     const uint32_t n = s.n, R = tm.base;
     for (uint32_t k = tm.lt; k < n; k += tm.T) {
@@ -289,7 +296,7 @@ __device__ void run_small(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps,
             if (k + 3 < n) L.w[R + k + 3] = w.w;
         }
         __syncthreads();
-        sort_into_b<D>(L, tm, n, 0, [sh](uint32_t w) { return w >> sh; });
+        sort_into_b<D, W>(L, tm, n, 0, [sh](uint32_t w) { return w >> sh; });
         // b (key order, old positions) -> a (key order, new positions)
         if (n > 0)
             batches<D, KERN, P>(s, tm, L.b + R, 0, n, [&](uint32_t r, const Rec<D> &o) { L.a[R + r] = o; });
@@ -304,11 +311,12 @@ __device__ void run_small(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps,
 
 // One system streamed through global memory by the whole workgroup (tm is
 // the workgroup as one team).
-template <int D, int KERN, int P>
-__device__ void run_large(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps, uint32_t bmean,
+template <int D, int KERN, int P, int W>
+__device__ void run_large(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nsteps, uint32_t bmean,
                           float *__restrict__ x, Rec<D> *__restrict__ state, Rec<D> *__restrict__ stage,
                           uint32_t *__restrict__ wst, uint32_t *__restrict__ flags)
 {
+    RBM_ENS_SHAPE;
     const uint32_t n = s.n, tid = threadIdx.x;
     const uint32_t nbk = (n + bmean - 1) / bmean;  // <= MAXB by the host's checks
     for (uint32_t k = tid; k < n; k += TPB) {
@@ -385,8 +393,9 @@ __device__ void run_large(Lds<D> &L, const Team &tm, StepArgs s, int64_t nsteps,
                 L.w[e] = wst[lo + e];
             }
             __syncthreads();
-            // sub-bucket: the next 12 bits of w nbk / 2^32 below the bucket
-            sort_into_b<D>(L, tm, cnt, nc, [nbk](uint32_t w) { return (w * nbk) >> 20; });
+            // sub-bucket: the next log2(4 W) bits of w nbk / 2^32 below the bucket
+            const uint32_t sh = 32u - tm.lg;
+            sort_into_b<D, W>(L, tm, cnt, nc, [nbk, sh](uint32_t w) { return (w * nbk) >> sh; });
             // L.b[0..nc) carried records (ranks lo - nc ..), then this bucket
             const uint32_t r0 = lo - nc;
             uint32_t r1;  // end of the complete batches
@@ -438,10 +447,11 @@ __device__ __forceinline__ StepArgs args_of(const StepArgs &base, const Sys &sy,
     return s;
 }
 
-template <int D, int KERN, int P>
-__global__ __launch_bounds__(TPB) void k_ensemble(EnsLaunch e)
+template <int D, int KERN, int P, int W>
+__global__ __launch_bounds__(W, 4) void k_ensemble(EnsLaunch e)
 {
-    __shared__ Lds<D> L;
+    RBM_ENS_SHAPE;
+    __shared__ Lds<D, W> L;
     const Sys *__restrict__ sys = (const Sys *)e.sys;
     for (;;) {
         if (threadIdx.x == 0) L.item = atomicAdd(e.next, 1u);
@@ -455,11 +465,11 @@ __global__ __launch_bounds__(TPB) void k_ensemble(EnsLaunch e)
             const Sys sy = sys[id];
             const StepArgs s = args_of(e.base, sy, id);
             float *xs = e.x + (size_t)sy.off * D;
-            const Team tm = make_team(TPB);
+            const Team tm = make_team(W);
             if (sy.n <= e.lds_max)
-                run_small<D, KERN, P>(L, tm, s, e.nsteps, xs);
+                run_small<D, KERN, P, W>(L, tm, s, e.nsteps, xs);
             else
-                run_large<D, KERN, P>(L, tm, s, e.nsteps, e.bmean, xs, (Rec<D> *)e.state + sy.off,
+                run_large<D, KERN, P, W>(L, tm, s, e.nsteps, e.bmean, xs, (Rec<D> *)e.state + sy.off,
                                       (Rec<D> *)e.stage + sy.off, e.wst + sy.off, e.flags);
         } else {
             const Team tm = make_team(e.team);
@@ -471,7 +481,7 @@ __global__ __launch_bounds__(TPB) void k_ensemble(EnsLaunch e)
                 sy = sys[id];
             }
             const StepArgs s = args_of(e.base, sy, id);
-            run_small<D, KERN, P>(L, tm, s, e.nsteps, e.x + (size_t)sy.off * D);
+            run_small<D, KERN, P, W>(L, tm, s, e.nsteps, e.x + (size_t)sy.off * D);
         }
         __syncthreads();
     }
@@ -488,16 +498,22 @@ __global__ void k_zero(uint32_t *p)
 
 namespace {
 
+template <int D, int KERN, int W>
+hipError_t ens_dkw(const EnsLaunch &e, hipStream_t st)
+{
+    switch (e.base.p) {
+    case 2: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 2, W>), dim3(e.grid), dim3(W), 0, st, e); break;
+    case 4: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 4, W>), dim3(e.grid), dim3(W), 0, st, e); break;
+    case 8: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 8, W>), dim3(e.grid), dim3(W), 0, st, e); break;
+    default: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 0, W>), dim3(e.grid), dim3(W), 0, st, e); break;
+    }
+    return hipGetLastError();
+}
+
 template <int D, int KERN>
 hipError_t ens_dk(const EnsLaunch &e, hipStream_t st)
 {
-    switch (e.base.p) {
-    case 2: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 2>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
-    case 4: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 4>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
-    case 8: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 8>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
-    default: hipLaunchKernelGGL((ens::k_ensemble<D, KERN, 0>), dim3(e.grid), dim3(ens::TPB), 0, st, e); break;
-    }
-    return hipGetLastError();
+    return e.wg == 512 ? ens_dkw<D, KERN, 512>(e, st) : ens_dkw<D, KERN, 1024>(e, st);
 }
 
 }  // namespace

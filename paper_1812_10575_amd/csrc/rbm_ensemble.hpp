@@ -26,7 +26,8 @@ struct EnsLaunch {
     int64_t nsteps;
     uint32_t nitems;    // work items in the queue
     uint32_t lds_max;   // a whole-workgroup system up to this size stays in LDS
-    uint32_t team;      // threads per system of a grouped item (64 .. 1024)
+    uint32_t wg;        // threads per workgroup: 1024 (4096 records of LDS) or 512 (2048)
+    uint32_t team;      // threads per system of a grouped item (64 .. wg)
     uint32_t bmean;     // mean bucket of a streamed system
     uint32_t grid;      // persistent workgroups
     void *sys;          // per-system table (EnsSys)

@@ -117,7 +117,8 @@ def test_streamed_path_equals_lds_path():
     a = run(ens, x0, 0, 5)
     b = run(ens, x0, 0, 5, lds_max=64)
     c = run(ens, x0, 0, 5, lds_max=1024, grid=3)
-    assert np.array_equal(a, b) and np.array_equal(a, c)
+    d = run(ens, x0, 0, 5, wg=512, lds_max=64)
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
 
 
 def test_graph_and_direct_launch_agree_and_replay():
@@ -154,6 +155,10 @@ def test_zero_steps_and_bad_arguments():
         run(make([64, rbm.ENS_MAXN + 1]), np.zeros((64 + rbm.ENS_MAXN + 1, 2), np.float32), 0, 1)
     with pytest.raises(rbm.RbmError):
         run(ens, x0, 0, 1, lds_max=rbm.ENS_LDS + 1)
+    with pytest.raises(rbm.RbmError):
+        run(ens, x0, 0, 1, wg=512, lds_max=2049)
+    with pytest.raises(rbm.RbmError):
+        run(ens, x0, 0, 1, wg=256)
 
 
 def test_every_tile_gives_the_same_result():
@@ -162,7 +167,8 @@ def test_every_tile_gives_the_same_result():
     x0 = x0_of(ens, 10)
     ref = run(ens, x0, 2, 4)
     for tile in (dict(team=64), dict(team=128, bucket=1024), dict(team=1024, bucket=3072, lds_max=2048),
-                 dict(team=512, bucket=256, lds_max=1)):
+                 dict(team=512, bucket=256, lds_max=1), dict(wg=512), dict(wg=512, team=64, bucket=1536),
+                 dict(wg=512, team=512, bucket=512, lds_max=600)):
         assert np.array_equal(run(ens, x0, 2, 4, **tile), ref), tile
 
 
