@@ -213,16 +213,39 @@ def test_force_mse_follows_lemma_3_1(name, n, p):
 
 
 def test_full_size_attrep3d_step():
-    """The headline size N = 2^24, p = 8: the whole permutation bit-exact and
-    every particle within 1e-5 after one step, in the launch configuration
-    the benchmark times."""
+    """The headline size N = 2^24, p = 8, run as the benchmark runs it (9 steps
+    in one call: a group of 8 steps sharing one launch of the key passes,
+    then one more): the slot order after every step bit-exact (the oracle
+    chains its permutations), then one more step from the GPU's state,
+    every particle within 1e-5."""
     w = rbm_inputs.params_of("attrep3d-n2^24-p8")
     say("full size", w["n"])
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, 9)
+    rbm.rbm_check(ctx)
+    x9, s9 = state(ctx)
+    so = np.arange(w["n"], dtype=np.uint32)
+    for m in range(9):
+        so = ora.permutation(op(w), m, so)
+    assert np.array_equal(s9, so)
+    rbm.rbm_step(ctx)
+    rbm.rbm_check(ctx)
+    x10, s10 = state(ctx)
+    xo, so10 = ora.rbm_step(op(w), w["p"], 9, x9.astype(np.float64), s9)
+    assert np.array_equal(s10, so10)
+    assert e_rel(x10, xo) <= 1e-5
+
+
+def test_largest_supported_size():
+    """N = 2^25 (the largest the plan supports: 32768 fine buckets), p = 3
+    with a remainder of 2: permutation bit-exact and e1 <= 1e-5."""
+    w = rbm_inputs.params_of("dyson1d-n2^20-p2", n=1 << 25, p=3)
+    say("max size", w["n"])
     ctx, x0 = start(w)
     rbm.rbm_step(ctx)
     rbm.rbm_check(ctx)
     x1, s1 = state(ctx)
-    xo, so = ora.rbm_step(op(w), w["p"], 0, x0, np.arange(w["n"], dtype=np.uint32))
+    xo, so = ora.rbm_step(op(w), w["p"], 0, x0.astype(np.float64), np.arange(w["n"], dtype=np.uint32))
     assert np.array_equal(s1, so)
     assert e_rel(x1, xo) <= 1e-5
 
