@@ -170,7 +170,11 @@ def force_mse(args) -> dict:
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     ids = torch.from_numpy(np.random.default_rng(7).choice(n, 1 << 16, replace=False).astype(np.int32)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     fdir, m2 = rbm.direct_moments(mk(), x, ids)
+    torch.cuda.synchronize()
+    pair_rate = ids.numel() * (n - 1) / (time.perf_counter() - t0)  # Gaussian pairs per second, d = 2
     # Lemma 3.1: E|F^RBM - F|^2 = (1/(p-1) - 1/(N-1)) Lambda_i,
     # Lambda_i = (N-1)/(N-2) (m2_i - |F_i|^2)
     f64 = fdir.double()
@@ -199,8 +203,8 @@ def force_mse(args) -> dict:
     gain = mse_plain / mse_cv
     # Lemma 3.1: MSE(p) = (1/(p-1) - 1/(N-1)) Lambda, so equal MSE needs
     # 1/(p'-1) - 1/(N-1) = (1 - 1/(N-1)) / gain
-    pp = int(math.ceil(1.0 + 1.0 / ((1.0 - 1.0 / (n - 1)) / gain + 1.0 / (n - 1))))
-    pp = max(2, min(pp, 64))
+    pp_equal = int(math.ceil(1.0 + 1.0 / ((1.0 - 1.0 / (n - 1)) / gain + 1.0 / (n - 1))))
+    pp = max(2, min(pp_equal, 64))
     plain_pp = rbm.rbm_init(mk(p=pp), x)
     mse_pp = mse_of(plain_pp)
     out = {"workload": "gauss2d-n2^22-p2", "n": n, "p": 2, "subset": int(ids.numel()), "divisions": 16,
@@ -208,7 +212,13 @@ def force_mse(args) -> dict:
            "train": {"pairs": args.train_steps * args.train_batch, "adam_steps": args.train_steps,
                      "batch": args.train_batch, "seconds": round(t_train, 3),
                      "loss_first": float(losses[:16].mean().cpu()), "loss_last": float(losses[-16:].mean().cpu())},
-           "equal_mse": {"p_plain": pp, "mse_plain": mse_pp,
+           "equal_mse": {"p_equal": pp_equal,
+                         # plain RBM-1 at p_equal needs (p_equal - 1) / 2 pair evaluations per
+                         # particle at the very least; at the direct sum's pair rate on this
+                         # GPU that bounds its throughput from above
+                         "plain_bound_at_p_equal": 2.0 * pair_rate / max(pp_equal - 1, 1),
+                         "pair_rate": pair_rate,
+                         "p_plain": pp, "mse_plain": mse_pp,
                          "plain_particle_steps_per_s": rate_of(plain_pp),
                          "cv_particle_steps_per_s": rate_of(cvctx),
                          "plain_p2_particle_steps_per_s": rate_of(rbm.rbm_init(mk(), x))}}
