@@ -391,3 +391,16 @@ def test_semicircle_cdf_closed_form(ora):
     rho = np.sqrt(np.maximum(2 - x ** 2, 0)) / math.pi
     assert np.trapezoid(rho, x) == pytest.approx(1.0, abs=1e-6)
     assert np.trapezoid(x * x * rho, x) == pytest.approx(0.5, abs=1e-6)
+
+
+def test_ks_distance_matches_the_library_statistic(ora):
+    """The KS distance is scipy's two-sided one-sample statistic, on samples
+    from the semicircle law and from a shifted law; and the semicircle of
+    rbm_inputs lands within the 1% band for 2^20 samples."""
+    from scipy import stats
+    for shift in (0.0, 0.05):
+        x = rbm_inputs.semicircle(20000, radius=math.sqrt(2.0), seed=11).astype(np.float64)[:, 0] + shift
+        want = stats.kstest(x, lambda t: ora.semicircle_cdf(t)).statistic
+        assert ora.ks_distance(x, ora.semicircle_cdf) == pytest.approx(want, abs=1e-12)
+    big = rbm_inputs.semicircle(1 << 20, radius=math.sqrt(2.0), seed=12).astype(np.float64)
+    assert ora.ks_distance(big, ora.semicircle_cdf) < 0.01
