@@ -100,7 +100,9 @@ rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_
 rbm_status rbm_step(rbm_ctx *ctx, void *stream);
 
 /* nsteps consecutive rbm_step calls (bitwise identical to calling rbm_step
- * nsteps times). */
+ * nsteps times).  The bucket counts and starts of a step depend only on the
+ * step index and the slot indices, so they are computed for groups of up to
+ * 8 consecutive steps with one launch of each key kernel. */
 rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream);
 
 /* Current positions, [N][d] FP32 by id. */
@@ -125,7 +127,8 @@ rbm_status rbm_step_index(const rbm_ctx *ctx, int64_t *m);
 rbm_status rbm_check(rbm_ctx *ctx, void *stream);
 
 /* Kernels of one step, for rbm_phase_times (a kernel a step does not need
- * measures 0). */
+ * measures 0; the key phases of a group of steps are timed with its first
+ * step, so their average over the recorded steps is the cost per step). */
 enum {
     RBM_PHASE_KEYCOUNT = 0,  /* fine-bucket histogram of the PERM words per slot tile */
     RBM_PHASE_KEYSUM = 1,    /* fine-bucket totals */
@@ -158,9 +161,12 @@ rbm_status rbm_destroy(rbm_ctx *ctx);
  *   F_i = a(X_i).(S - c(X_i))/(N-1)
  *         + 1/(s-1) sum_{j in batch, j != i} [K(X_i - X_j) - a(X_i).c(X_j)],
  *   S = sum_j c(X_j) (FP64),
- * with MLPs a, c: R^2 -> R^32 (2 -> 64 -> 64 -> 32, GELU after the hidden
- * layers; outputs read as [component 2][rank 16]) evaluated with BF16 matrix
- * instructions (FP32 accumulation).  Parameters of one net, FP32, in order:
+ * with MLPs a, c: R^2 -> R^32 (2 -> 64 -> 64 -> 32, GELU in its tanh form,
+ * z sigma(2 sqrt(2/pi) z (1 + 0.044715 z^2)), after the hidden layers;
+ * outputs read as [component 2][rank 16]) evaluated with BF16 matrix
+ * instructions (FP32 accumulation).  A step evaluates c once for every
+ * particle (for S, kept in the workspace) and a once; the workspace of a
+ * cv = 1 context adds 140 bytes per particle.  Parameters of one net, FP32, in order:
  * W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32]; a then c.
  * rbm_init initialises them (cv_init with the context's seed). */
 
@@ -203,11 +209,13 @@ rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids
  * nsys independent RBM-1 systems sharing the model parameters, system s with
  * N_s particles, Philox key seed_s and counter word 3 = s: each follows the
  * definitions of a standalone run with those values (its division is the
- * standalone one bit for bit).  All systems run in one persistent launch:
- * workgroups take systems from a queue ordered by decreasing N_s.  Systems
- * of up to tile.lds_max particles (<= RBM_ENS_LDS) stay in LDS for all
- * steps; larger ones (up to RBM_ENS_MAXN) are streamed through the
- * workspace. */
+ * standalone one bit for bit, and with it every position).  All systems run
+ * in one persistent launch: workgroups take work items from a queue ordered
+ * by decreasing N_s; an item is one system, or a group of wg / team systems
+ * of at most 4 team particles run side by side by teams of threads.  A
+ * system run by a whole workgroup stays in LDS for all steps up to
+ * tile.lds_max particles (<= RBM_ENS_LDS); larger ones (up to RBM_ENS_MAXN)
+ * are streamed through the workspace. */
 typedef struct {
     int32_t d;        /* space dimension: 2 */
     int32_t kernel;   /* rbm_kernel */
@@ -227,7 +235,7 @@ typedef struct {
                          particles, run wg / team to a workgroup: a power of
                          two in 64..wg (default 256; wg: one system per
                          workgroup) */
-    int32_t bucket;   /* mean bucket of a streamed system, 256..3 wg / 4
+    int32_t bucket;   /* mean bucket of a streamed system, 256..3 wg
                          (default wg); at most 256 buckets per system */
     int32_t wg;       /* threads per workgroup: 1024 (4096 records of LDS, one
                          workgroup per compute unit) or 512 (2048 records, two);
@@ -246,11 +254,12 @@ rbm_status ensemble_workspace_size(const rbm_ensemble *e, const int64_t *h_n, si
 /* Runs steps step0 .. step0 + nsteps - 1 of every system.  Each call starts
  * every system with slot k holding particle k (as rbm_init with no slots at
  * step step0), so one call of 2k steps and two calls of k steps differ in
- * their divisions.  h_n, h_seed: host arrays of nsys sizes and Philox keys.  d_x: packed FP32 positions
- * [sum N_s][d], system by system, each by particle id; read at the start and
- * overwritten with the final positions.  graph != 0: the launch is recorded
- * into a hipGraph and replayed once.  Waits for completion and returns
- * RBM_ERR_DEVICE if a device-side check failed. */
+ * their divisions.  h_n, h_seed: host arrays of nsys sizes and Philox keys.
+ * d_x: packed FP32 positions [sum N_s][d], system by system, each by
+ * particle id; read at the start and overwritten with the final positions.
+ * tile: launch shape (NULL: defaults).  graph != 0: the launch is recorded
+ * into a hipGraph on a private stream and replayed once.  Waits for
+ * completion and returns RBM_ERR_DEVICE if a device-side check failed. */
 rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_t *h_seed,
                         float *d_x, int64_t step0, int64_t nsteps,
                         const rbm_ensemble_tile *tile, void *d_ws, size_t ws_bytes,
