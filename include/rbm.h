@@ -246,7 +246,7 @@ typedef struct {
 #define RBM_ENS_MAXN (256 * 1024)
 
 /* Workspace bytes for these systems (a 256-byte aligned device buffer of
- * about 28 bytes per particle plus the system table); h_n: host array of nsys
+ * about 32 bytes per particle plus the system table); h_n: host array of nsys
  * sizes.  Errors: RBM_ERR_INVALID for a size outside p..RBM_ENS_MAXN,
  * RBM_ERR_UNSUPPORTED for d != 2 or more than 2^31 - 1 particles in all. */
 rbm_status ensemble_workspace_size(const rbm_ensemble *e, const int64_t *h_n, size_t *bytes);

@@ -611,7 +611,7 @@ static_assert(RBM_ENS_LDS == 4096 && RBM_ENS_MAXN == 256 * 1024, "ensemble limit
 namespace {
 
 struct EnsLayout {
-    size_t sys, order, items, ctl, state, stage, wst, total;
+    size_t sys, order, items, ctl, state, stage, wst, wst2, total;
     uint64_t nsum;
 };
 
@@ -649,6 +649,7 @@ rbm_status ens_check(const rbm_ensemble *e, const int64_t *h_n, EnsLayout *lay)
     lay->state = take(nsum * sizeof(rbm::Rec<2>));
     lay->stage = take(nsum * sizeof(rbm::Rec<2>));
     lay->wst = take(nsum * 4);
+    lay->wst2 = take(nsum * 4);
     lay->total = off;
     return RBM_OK;
 }
@@ -773,6 +774,7 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     L.state = ws + lay.state;
     L.stage = ws + lay.stage;
     L.wst = (uint32_t *)(ws + lay.wst);
+    L.wst2 = (uint32_t *)(ws + lay.wst2);
 
     if (!graph) {
         he = rbm::launch_ensemble(L, e->kernel, hs);

@@ -54,8 +54,9 @@ struct Lds {
     uint32_t cnt[4 * W];  // sub-bucket counts, then starts (team slices of 4 T)
     uint32_t tot[W / 64]; // records per team slice
     uint32_t scan[W / 64];
-    uint32_t hist[MAXB + 1];
-    uint32_t cur[MAXB];
+    uint32_t hist[MAXB + 1];   // bucket starts of the current step
+    uint32_t hist2[MAXB + 1];  // ... of the next step
+    uint32_t cur[MAXB];        // scatter cursors
     uint32_t item;
     uint32_t ncarry;
 };
@@ -309,88 +310,105 @@ __device__ void run_small(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nste
     }
 }
 
+// Bucket plan of step m for a streamed system: histogram of its PERM words
+// over all slots (no memory read), exclusive scan into starts[0..nbk] and
+// the scatter cursors L.cur.  Ends with a barrier.
+template <int D, int W>
+__device__ void bucket_plan(Lds<D, W> &L, StepArgs s, uint32_t m, uint32_t nbk, uint32_t *starts)
+{
+    RBM_ENS_SHAPE;
+    const uint32_t n = s.n, tid = threadIdx.x;
+    s.m = m;
+    for (uint32_t i = tid; i <= nbk; i += TPB) starts[i] = 0;
+    __syncthreads();
+    for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+        const uint4 w = words4(s, k);
+        atomicAdd(&starts[__umulhi(w.x, nbk)], 1u);
+        if (k + 1 < n) atomicAdd(&starts[__umulhi(w.y, nbk)], 1u);
+        if (k + 2 < n) atomicAdd(&starts[__umulhi(w.z, nbk)], 1u);
+        if (k + 3 < n) atomicAdd(&starts[__umulhi(w.w, nbk)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        // exclusive scan of nbk <= 256 counts by one wavefront
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = tid * 4 + k;
+            v[k] = i < nbk ? starts[i] : 0u;
+            sum += v[k];
+        }
+        const uint32_t inc = wave_inclusive_scan_e(sum);
+        uint32_t run = inc - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = tid * 4 + k;
+            if (i < nbk) {
+                starts[i] = run;
+                L.cur[i] = run;
+            }
+            run += v[k];
+        }
+        if (tid == 0) starts[nbk] = n;
+    }
+    __syncthreads();
+}
+
 // One system streamed through global memory by the whole workgroup (tm is
-// the workgroup as one team).
+// the workgroup as one team).  Between steps the records sit in the bucket
+// order of the next step's words, in one of two buffers: a step reads its
+// buckets in order, sorts each in LDS (the batch cut by a bucket's end is
+// carried to the next bucket), evaluates the batches and writes every
+// updated record straight into its bucket of the next step (the next word
+// of a record depends only on its rank, its next slot), so each step moves
+// a record once in and once out.  The last step writes positions by id.
 template <int D, int KERN, int P, int W>
 __device__ void run_large(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nsteps, uint32_t bmean,
-                          float *__restrict__ x, Rec<D> *__restrict__ state, Rec<D> *__restrict__ stage,
-                          uint32_t *__restrict__ wst, uint32_t *__restrict__ flags)
+                          float *__restrict__ x, Rec<D> *__restrict__ bufA, Rec<D> *__restrict__ bufB,
+                          uint32_t *__restrict__ wA, uint32_t *__restrict__ wB, uint32_t *__restrict__ flags)
 {
     RBM_ENS_SHAPE;
     const uint32_t n = s.n, tid = threadIdx.x;
     const uint32_t nbk = (n + bmean - 1) / bmean;  // <= MAXB by the host's checks
-    for (uint32_t k = tid; k < n; k += TPB) {
-        Rec<D> r;
+    const uint32_t m0 = s.m;
+    uint32_t *starts = L.hist, *next = L.hist2;
+    // step m0: slot k holds particle k
+    bucket_plan<D, W>(L, s, m0, nbk, starts);
+    for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
+        const uint4 w = words4(s, k);
 #pragma unroll
-        for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)k * D + c];
-        r.id = k;
-        state[k] = r;
+        for (uint32_t j = 0; j < 4; ++j) {
+            if (k + j < n) {
+                const uint32_t wj = word_of(w, j);
+                const uint32_t pos = atomicAdd(&L.cur[__umulhi(wj, nbk)], 1u);
+                Rec<D> r;
+#pragma unroll
+                for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)(k + j) * D + c];
+                r.id = k + j;
+                bufA[pos] = r;
+                wA[pos] = wj;
+            }
+        }
     }
     __syncthreads();
-    const uint32_t m0 = s.m;
     for (int64_t t = 0; t < nsteps; ++t) {
         s.m = m0 + (uint32_t)t;
-        // 1. bucket histogram of the words (no memory read)
-        for (uint32_t i = tid; i <= nbk; i += TPB) L.hist[i] = 0;
-        __syncthreads();
-        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
-            const uint4 w = words4(s, k);
-            atomicAdd(&L.hist[__umulhi(w.x, nbk)], 1u);
-            if (k + 1 < n) atomicAdd(&L.hist[__umulhi(w.y, nbk)], 1u);
-            if (k + 2 < n) atomicAdd(&L.hist[__umulhi(w.z, nbk)], 1u);
-            if (k + 3 < n) atomicAdd(&L.hist[__umulhi(w.w, nbk)], 1u);
-        }
-        __syncthreads();
-        if (tid < 64) {
-            // exclusive scan of nbk <= 256 counts by one wavefront
-            uint32_t v[4], sum = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t i = tid * 4 + k;
-                v[k] = i < nbk ? L.hist[i] : 0u;
-                sum += v[k];
-            }
-            const uint32_t inc = wave_inclusive_scan_e(sum);
-            uint32_t run = inc - sum;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t i = tid * 4 + k;
-                if (i < nbk) {
-                    L.hist[i] = run;
-                    L.cur[i] = run;
-                }
-                run += v[k];
-            }
-            if (tid == 0) L.hist[nbk] = n;
-        }
-        __syncthreads();
-        // 2. records to their buckets (order inside a bucket is free)
-        for (uint32_t k = 4 * tid; k < n; k += 4 * TPB) {
-            const uint4 w = words4(s, k);
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
-                if (k + j < n) {
-                    const uint32_t wj = word_of(w, j);
-                    const uint32_t pos = atomicAdd(&L.cur[__umulhi(wj, nbk)], 1u);
-                    stage[pos] = state[k + j];
-                    wst[pos] = wj;
-                }
-            }
-        }
-        __syncthreads();
-        // 3. buckets in order; the batch cut by a bucket's end is carried
+        const bool last = t == nsteps - 1;
+        if (!last) bucket_plan<D, W>(L, s, s.m + 1, nbk, next);  // cursors of the next step in L.cur
+        StepArgs sn = s;
+        sn.m = s.m + 1;
         if (tid == 0) L.ncarry = 0;
         __syncthreads();
         for (uint32_t bk = 0; bk < nbk; ++bk) {
-            const uint32_t lo = L.hist[bk], hi = L.hist[bk + 1], cnt = hi - lo;
+            const uint32_t lo = starts[bk], hi = starts[bk + 1], cnt = hi - lo;
             const uint32_t nc = L.ncarry;
             if (nc + cnt > (uint32_t)CAP) {  // far beyond any bucket's spread: flag, give up the step
                 if (tid == 0) atomicOr(flags, 1u);
                 break;
             }
             for (uint32_t e = tid; e < cnt; e += TPB) {
-                L.a[e] = stage[lo + e];
-                L.w[e] = wst[lo + e];
+                L.a[e] = bufA[lo + e];
+                L.w[e] = wA[lo + e];
             }
             __syncthreads();
             // sub-bucket: the next log2(4 W) bits of w nbk / 2^32 below the bucket
@@ -407,7 +425,27 @@ __device__ void run_large(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nste
                 const uint32_t last_start = (s.nbat - 1) * s.p;
                 if (r1 > last_start) r1 = last_start > r0 ? last_start : r0;
             }
-            batches<D, KERN, P>(s, tm, L.b, r0, r1, [&](uint32_t r, const Rec<D> &o) { state[r] = o; });
+            // a thread emits the ranks of a batch in order: one Philox block
+            // gives the next words of 4 consecutive ranks
+            uint32_t wk = 0xffffffffu;
+            uint4 w4 = make_uint4(0u, 0u, 0u, 0u);
+            batches<D, KERN, P>(s, tm, L.b, r0, r1, [&](uint32_t r, const Rec<D> &o) {
+                if (last) {
+                    if (o.id < n) {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) x[(size_t)o.id * D + c] = o.x[c];
+                    }
+                } else {
+                    if ((r >> 2) != wk) {
+                        wk = r >> 2;
+                        w4 = words4(sn, r & ~3u);
+                    }
+                    const uint32_t wr = word_of(w4, r & 3u);
+                    const uint32_t pos = atomicAdd(&L.cur[__umulhi(wr, nbk)], 1u);
+                    bufB[pos] = o;
+                    wB[pos] = wr;
+                }
+            });
             __syncthreads();
             const uint32_t keep = hi - r1;
             const uint32_t from = r1 - r0;
@@ -427,11 +465,16 @@ __device__ void run_large(Lds<D, W> &L, const Team &tm, StepArgs s, int64_t nste
             __syncthreads();
         }
         __syncthreads();
-    }
-    for (uint32_t k = tid; k < n; k += TPB) {
-        const Rec<D> r = state[k];
-#pragma unroll
-        for (int c = 0; c < D; ++c) x[(size_t)r.id * D + c] = r.x[c];
+        // the next step reads the buffers just written, with the next starts
+        Rec<D> *tb = bufA;
+        bufA = bufB;
+        bufB = tb;
+        uint32_t *tw = wA;
+        wA = wB;
+        wB = tw;
+        uint32_t *ts = starts;
+        starts = next;
+        next = ts;
     }
 }
 
@@ -470,7 +513,7 @@ __global__ __launch_bounds__(W, 4) void k_ensemble(EnsLaunch e)
                 run_small<D, KERN, P, W>(L, tm, s, e.nsteps, xs);
             else
                 run_large<D, KERN, P, W>(L, tm, s, e.nsteps, e.bmean, xs, (Rec<D> *)e.state + sy.off,
-                                      (Rec<D> *)e.stage + sy.off, e.wst + sy.off, e.flags);
+                                         (Rec<D> *)e.stage + sy.off, e.wst + sy.off, e.wst2 + sy.off, e.flags);
         } else {
             const Team tm = make_team(e.team);
             // teams beyond the item's systems run an empty system in step

@@ -35,8 +35,8 @@ struct EnsLaunch {
     const uint2 *items;     // item q: systems order[x .. x + y)
     uint32_t *next;     // queue counter; next[1]: error flags
     float *x;           // packed positions, by (system, id), in and out
-    void *state, *stage;
-    uint32_t *wst;
+    void *state, *stage;     // the two record buffers of the streamed systems
+    uint32_t *wst, *wst2;    // their PERM words
     uint32_t *flags;    // == next + 1
 };
 
