@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-K_GAUSS, K_SOFTCOULOMB, K_ATTREP = 0, 1, 2
+K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT = 0, 1, 2, 3
 
 
 class _Params(ctypes.Structure):
@@ -73,6 +73,7 @@ def _load():
     lib.ora_rbm_forces.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, f64p, u32p, f64p]
     lib.ora_direct_forces.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p]
     lib.ora_direct_moments.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p, f64p]
+    lib.ora_pair_flow.argtypes = [ctypes.c_int32, ctypes.c_double, f64p, f64p, f64p, f64p]
     lib.ora_rbm_step.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, f64p, u32p]
     lib.ora_rbm_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_int64, f64p, u32p]
@@ -211,6 +212,27 @@ def direct_step(prm: Params, m: int, x) -> np.ndarray:
 # --------------------------------------------------------------------------
 # diagnostics
 # --------------------------------------------------------------------------
+
+def pair_flow(d: int, t: float, xi, xj):
+    """Exact flow over time t of a batch of two particles under
+    K(x) = x/|x|^2 (Sec. 2.3 splitting, Sec. 4.2): returns (yi, yj)."""
+    a, b = _f64(xi).copy(), _f64(xj).copy()
+    yi, yj = np.zeros(d), np.zeros(d)
+    _load().ora_pair_flow(d, t, _p(a, ctypes.c_double), _p(b, ctypes.c_double), _p(yi, ctypes.c_double),
+                          _p(yj, ctypes.c_double))
+    return yi, yj
+
+
+def semicircle_cdf_r(x, radius):
+    """CDF of the semicircle law of the given radius R,
+    rho(x) = 2 sqrt(R^2 - x^2) / (pi R^2); R^2 = 2 sigma(t) gives the
+    analytic density of Sec. 4.2, rho(x, t) = sqrt(2 sigma(t) - x^2) /
+    (sigma(t) pi), sigma(t) = 1 + e^{-2t}."""
+    R = float(radius)
+    x = np.clip(np.asarray(x, np.float64), -R, R)
+    r = np.sqrt(np.maximum(R * R - x * x, 0.0))
+    return 0.5 + x * r / (math.pi * R * R) + np.arcsin(np.clip(x / R, -1.0, 1.0)) / math.pi
+
 
 def semicircle_cdf(x):
     """CDF of the semicircle law rho(x) = sqrt(2 - x^2) / pi (Sec. 4.2)."""

@@ -129,7 +129,7 @@ void ora_normals(uint64_t seed, uint32_t sys, uint32_t m, uint32_t id, double z[
 /* Model: the pair kernel K and the external field -grad V of eq. (1.2)     */
 /* ------------------------------------------------------------------------ */
 
-enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2 };
+enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2, ORA_K_COULOMB_SPLIT = 3 };
 
 typedef struct {
     int32_t d;          /* space dimension, 1..3 */
@@ -142,12 +142,14 @@ typedef struct {
     uint32_t sys;
 } ora_params;
 
-/* The three interaction kernels used by the workloads:
+/* The interaction kernels used by the workloads:
  *   GAUSS       K(x) = -x exp(-|x|^2)
  *   SOFTCOULOMB K(x) = x / (|x|^2 + a)         (a = eps^2; a = 1 gives the
  *                                               Sec. 4.1 kernel x/(1+x^2))
  *   ATTREP      K(x) = x / (|x|^2 + a) - x
- * All three are odd: K(-x) = -K(x), K(0) = 0. */
+ *   COULOMB_SPLIT K(x) = x / |x|^2, the singular kernel of Sec. 4.2, whose
+ *               steps use the splitting with the exact pair flow (below)
+ * All are odd: K(-x) = -K(x). */
 void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, double *out)
 {
     double r2 = 0.0;
@@ -157,6 +159,7 @@ void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, doubl
     case ORA_K_GAUSS:       s = -exp(-r2); break;
     case ORA_K_SOFTCOULOMB: s = 1.0 / (r2 + a); break;
     case ORA_K_ATTREP:      s = 1.0 / (r2 + a) - 1.0; break;
+    case ORA_K_COULOMB_SPLIT: s = 1.0 / r2; break;
     default:                s = 0.0; break;
     }
     for (int k = 0; k < d; ++k) out[k] = s * x[k];
@@ -296,16 +299,55 @@ static void euler_update(const ora_params *prm, int64_t n, uint32_t m,
     }
 }
 
+/* Exact flow over a time t of one batch of two particles under
+ * K(x) = x/|x|^2 with prefactor 1/(p-1) = 1 (Sec. 2.3, the splitting for
+ * singular K; the scheme of Sec. 4.2).  The centre c = (xi + xj)/2 does not
+ * move and u = xi - xj obeys du/dt = 2 u/|u|^2: its direction is kept and
+ * |u|^2 = |u0|^2 + 4t.  So yi = c + g u0/2, yj = c - g u0/2 with
+ * g = sqrt(1 + 4t/|u0|^2).  (The separation is g |u0|, hence the factor 1/2
+ * on the square root that the printed scheme of Sec. 4.2 leaves out.)  Two
+ * coincident particles (u0 = 0) stay at c. */
+void ora_pair_flow(int32_t d, double t, const double *xi, const double *xj, double *yi, double *yj)
+{
+    double c[3], u[3], r2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        c[k] = 0.5 * (xi[k] + xj[k]);
+        u[k] = xi[k] - xj[k];
+        r2 += u[k] * u[k];
+    }
+    const double g = r2 > 0.0 ? sqrt(1.0 + 4.0 * t / r2) : 0.0;
+    for (int k = 0; k < d; ++k) {
+        yi[k] = c[k] + 0.5 * g * u[k];
+        yj[k] = c[k] - 0.5 * g * u[k];
+    }
+}
+
 /* One RBM-1 step m (Algorithm 1): draw the division from the slot order,
  * compute batch forces at the old positions, update.  slots is replaced by
- * the new order (the sorted permutation). */
+ * the new order (the sorted permutation).  COULOMB_SPLIT (p = 2, N even):
+ * each pair moves by its exact flow over dt, then the external field and
+ * the noise act by one Euler-Maruyama step from the moved positions
+ * (Sec. 2.3 splitting, Sec. 4.2). */
 void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
                   double *x, uint32_t *slots)
 {
     const int d = prm->d;
     double *f = (double *)malloc((size_t)n * d * sizeof(double));
     ora_permutation(prm, n, m, slots, slots);
-    ora_rbm_forces(prm, n, p, x, slots, f);
+    if (prm->kernel == ORA_K_COULOMB_SPLIT) {
+        for (int64_t q = 0; q + 1 < n; q += 2) {
+            const int64_t i = slots[q], j = slots[q + 1];
+            double yi[3], yj[3];
+            ora_pair_flow(d, prm->dt, x + i * d, x + j * d, yi, yj);
+            for (int k = 0; k < d; ++k) {
+                x[i * d + k] = yi[k];
+                x[j * d + k] = yj[k];
+            }
+        }
+        for (int64_t e = 0; e < n * d; ++e) f[e] = 0.0;
+    } else {
+        ora_rbm_forces(prm, n, p, x, slots, f);
+    }
     euler_update(prm, n, m, f, x);
     free(f);
 }

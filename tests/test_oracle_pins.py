@@ -404,3 +404,99 @@ def test_ks_distance_matches_the_library_statistic(ora):
         assert ora.ks_distance(x, ora.semicircle_cdf) == pytest.approx(want, abs=1e-12)
     big = rbm_inputs.semicircle(1 << 20, radius=math.sqrt(2.0), seed=12).astype(np.float64)
     assert ora.ks_distance(big, ora.semicircle_cdf) < 0.01
+
+
+# --------------------------------------------------------------------------
+# splitting with the exact pair flow (Sec. 2.3; the Dyson scheme of Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def _rk4_pair(xi, xj, t, nsub=20000):
+    """The pair ODE dxi/dt = (xi - xj)/|xi - xj|^2 = -dxj/dt by classical RK4."""
+    y = np.concatenate([xi, xj]).astype(np.float64)
+    d = len(xi)
+
+    def rhs(v):
+        u = v[:d] - v[d:]
+        k = u / np.dot(u, u)
+        return np.concatenate([k, -k])
+
+    h = t / nsub
+    for _ in range(nsub):
+        k1 = rhs(y)
+        k2 = rhs(y + 0.5 * h * k1)
+        k3 = rhs(y + 0.5 * h * k2)
+        k4 = rhs(y + h * k3)
+        y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y[:d], y[d:]
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_pair_flow_solves_the_pair_ode(ora, d):
+    """The flow is the exact solution of the pair ODE: it agrees with a fine
+    RK4 integration, keeps the centre and the direction, and composes (flow
+    over t1 then t2 = flow over t1 + t2)."""
+    rng = np.random.default_rng(d)
+    xi, xj = rng.standard_normal(d), rng.standard_normal(d)
+    t = 0.3
+    yi, yj = ora.pair_flow(d, t, xi, xj)
+    ri, rj = _rk4_pair(xi, xj, t)
+    np.testing.assert_allclose(yi, ri, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(yj, rj, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(yi + yj, xi + xj, rtol=0, atol=1e-15)
+    u0, u = xi - xj, yi - yj
+    assert np.dot(u, u) == pytest.approx(np.dot(u0, u0) + 4 * t, rel=1e-14)
+    np.testing.assert_allclose(u / np.linalg.norm(u), u0 / np.linalg.norm(u0), atol=1e-15)
+    ai, aj = ora.pair_flow(d, 0.1, xi, xj)
+    bi, bj = ora.pair_flow(d, 0.2, ai, aj)
+    np.testing.assert_allclose(bi, yi, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(bj, yj, rtol=0, atol=1e-14)
+    # coincident particles stay at their centre
+    assert np.array_equal(ora.pair_flow(d, 0.1, xi, xi)[0], xi)
+
+
+def test_split_step_moves_pairs_then_applies_the_field(ora):
+    """A split step with sigma = 0: the batches are the pairs of the division,
+    each moved by its exact flow, then scaled by (1 - dt beta)."""
+    n, dt, beta = 10, 0.01, 1.0
+    prm = ora.Params(d=1, kernel=ora.K_COULOMB_SPLIT, kparam=0.0, beta=beta, sigma=0.0, dt=dt, seed=4)
+    x = rbm_inputs.normal(n, 1, seed=8).astype(np.float64)
+    x1, perm = ora.rbm_step(prm, 2, 0, x, np.arange(n))
+    for q in range(0, n, 2):
+        i, j = perm[q], perm[q + 1]
+        u0, u1 = x[i, 0] - x[j, 0], (x1[i, 0] - x1[j, 0]) / (1 - dt * beta)
+        assert u1 * u1 == pytest.approx(u0 * u0 + 4 * dt, rel=1e-13)
+        assert (x1[i, 0] + x1[j, 0]) == pytest.approx((1 - dt * beta) * (x[i, 0] + x[j, 0]), abs=1e-14)
+
+
+def test_semicircle_cdf_of_any_radius(ora):
+    for R in (1.0, math.sqrt(2.0), 2.0):
+        assert ora.semicircle_cdf_r(-R, R) == pytest.approx(0.0, abs=1e-15)
+        assert ora.semicircle_cdf_r(0.0, R) == pytest.approx(0.5, abs=1e-15)
+        assert ora.semicircle_cdf_r(R, R) == pytest.approx(1.0, abs=1e-15)
+        xs = np.linspace(-0.9 * R, 0.9 * R, 19)
+        h = 1e-6
+        dens = (ora.semicircle_cdf_r(xs + h, R) - ora.semicircle_cdf_r(xs - h, R)) / (2 * h)
+        np.testing.assert_allclose(dens, 2 * np.sqrt(R * R - xs ** 2) / (math.pi * R * R), rtol=1e-7)
+    x = np.linspace(-1.4, 1.4, 57)
+    np.testing.assert_allclose(ora.semicircle_cdf_r(x, math.sqrt(2.0)), ora.semicircle_cdf(x), atol=1e-15)
+
+
+def test_dyson_split_follows_the_analytic_density(ora):
+    """Sec. 4.2: from the radius-2 semicircle, RBM-1 with the exact pair flow
+    (beta = 1, sigma = 1/sqrt(N), tau = 1e-3) follows rho(x, t) =
+    sqrt(2 s(t) - x^2) / (s(t) pi), s(t) = 1 + e^{-2t}: KS distance and
+    second moment s(t)/2 at t = 0.5 and t = 3."""
+    n = 4096
+    prm = ora.Params(d=1, kernel=ora.K_COULOMB_SPLIT, kparam=0.0, beta=1.0, sigma=1 / math.sqrt(n),
+                     dt=1e-3, seed=3)
+    x = rbm_inputs.semicircle(n, 2.0, seed=5).astype(np.float64)
+    slots = None
+    m = 0
+    for t_end in (0.5, 3.0):
+        steps = int(round(t_end / 1e-3)) - m
+        x, slots = ora.rbm_run(prm, 2, m, steps, x, slots)
+        m += steps
+        sig = 1 + math.exp(-2 * t_end)
+        ks = ora.ks_distance(x[:, 0], lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig)))
+        assert ks < 0.02, (t_end, ks)
+        assert np.mean(x ** 2) == pytest.approx(sig / 2, abs=0.01), t_end
