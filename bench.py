@@ -258,6 +258,35 @@ def ensemble_rate(args) -> dict:
             "launch": "one persistent kernel replayed from a hipGraph; wall clock around the call"}
 
 
+def dyson_split(args) -> dict:
+    """Sec. 4.2's Dyson Brownian motion by the splitting with the exact pair
+    flow (K = 1/x, p = 2, beta = 1, sigma = 1/sqrt(N), tau = 1e-3), N = 2^20
+    from the radius-2 semicircle to t = 5: throughput and the KS distance to
+    the analytic density at the end."""
+    import numpy as np
+    import torch
+    import oracle as ora
+    import paper_1812_10575_amd as rbm
+    import rbm_inputs
+    w = rbm_inputs.params_of("dysonsplit1d-n2^20-p2")
+    prm = rbm.Params(**{k: w[k] for k in FIELDS})
+    ctx = rbm.rbm_init(prm, torch.from_numpy(rbm_inputs.workload(w["init"], w["n"], w["seed"])).cuda())
+    rbm.rbm_run(ctx, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbm.rbm_run(ctx, w["steps"] - 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rbm.rbm_check(ctx)
+    x = rbm.rbm_positions(ctx).cpu().numpy()[:, 0].astype(np.float64)
+    t_end = w["steps"] * w["dt"]
+    sig = 1 + math.exp(-2 * t_end)
+    ks = ora.ks_distance(x, lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig)))
+    return {"workload": "dysonsplit1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": t_end,
+            "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
+            "ks_vs_analytic": ks, "m2": float(np.mean(x * x)), "m2_analytic": sig / 2}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +395,8 @@ def main() -> int:
         out["force_mse"] = force_mse(args)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_rate(args)
+    if not args.no_sweep:
+        out["dyson_split"] = dyson_split(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

@@ -53,8 +53,19 @@ typedef enum {
  *   RBM_K_GAUSS       K(x) = -x exp(-|x|^2)
  *   RBM_K_SOFTCOULOMB K(x) = x / (|x|^2 + a)   (a = 1: the kernel of Sec. 4.1;
  *                                               small a: softened 1/x of Sec. 4.2)
- *   RBM_K_ATTREP      K(x) = x / (|x|^2 + a) - x                              */
-typedef enum { RBM_K_GAUSS = 0, RBM_K_SOFTCOULOMB = 1, RBM_K_ATTREP = 2 } rbm_kernel;
+ *   RBM_K_ATTREP      K(x) = x / (|x|^2 + a) - x
+ *   RBM_K_COULOMB_SPLIT K(x) = x / |x|^2 (a must be 0), stepped by the
+ *                     splitting of Sec. 2.3 with p = 2 (N even): each pair moves
+ *                     by its exact flow over dt (centre fixed, direction kept,
+ *                     |X^i - X^j|^2 grows by 4 dt: the scheme of Sec. 4.2 for the
+ *                     Dyson Brownian motion), then X += -dt beta X + sigma sqrt(dt) z.
+ *                     Forces (rbm_forces, direct_*) are those of x/|x|^2.     */
+typedef enum {
+    RBM_K_GAUSS = 0,
+    RBM_K_SOFTCOULOMB = 1,
+    RBM_K_ATTREP = 2,
+    RBM_K_COULOMB_SPLIT = 3
+} rbm_kernel;
 
 /* Model, method and stream parameters.  V(x) = beta |x|^2 / 2. */
 typedef struct {

@@ -31,6 +31,7 @@ SYMBOLS = (
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
+RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT = 0, 1, 2, 3
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
 

@@ -66,8 +66,10 @@ rbm_status check_params(const rbm_params *prm)
 {
     if (!prm) return fail(RBM_ERR_INVALID, "params is NULL");
     if (prm->d < 1 || prm->d > 3) return fail(RBM_ERR_INVALID, "d = %d not in 1..3", prm->d);
-    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_ATTREP)
+    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_COULOMB_SPLIT)
         return fail(RBM_ERR_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == RBM_K_COULOMB_SPLIT && prm->kparam != 0.0)
+        return fail(RBM_ERR_INVALID, "the split Coulomb kernel has no softening (kparam must be 0)");
     if (prm->n < 2) return fail(RBM_ERR_INVALID, "N = %lld < 2", (long long)prm->n);
     if (prm->n > RBM_MAX_N)
         return fail(RBM_ERR_UNSUPPORTED, "N = %lld above the supported %lld", (long long)prm->n,
@@ -85,10 +87,20 @@ rbm_status check_params(const rbm_params *prm)
     if (!(prm->kparam >= 0.0) || !std::isfinite(prm->kparam))
         return fail(RBM_ERR_INVALID, "kparam must be >= 0");
     if (!std::isfinite(prm->beta)) return fail(RBM_ERR_INVALID, "beta must be finite");
+    if (prm->kernel == RBM_K_COULOMB_SPLIT && (prm->p != 2 || prm->n % 2 != 0))
+        return fail(RBM_ERR_UNSUPPORTED, "the exact pair flow needs p = 2 and an even N");
     if (prm->n > RBM_SINGLE_CAP && prm->p > RBM_MAX_P_MULTI)
         return fail(RBM_ERR_UNSUPPORTED, "p = %d above %d needs N <= %d", prm->p, RBM_MAX_P_MULTI,
                     RBM_SINGLE_CAP);
     return RBM_OK;
+}
+
+// The force kernel of the kernels: the split Coulomb kernel evaluates its
+// forces (rbm_forces, the direct sum) as x/|x|^2, the soft Coulomb kernel
+// with a = 0; its steps differ by StepArgs.split.
+int kern_of(int kernel)
+{
+    return kernel == RBM_K_COULOMB_SPLIT ? RBM_K_SOFTCOULOMB : kernel;
 }
 
 Plan make_plan(const rbm_params *prm)
@@ -99,7 +111,7 @@ Plan make_plan(const rbm_params *prm)
     pl.p = (uint32_t)prm->p;
     pl.nbat = pl.n / pl.p;
     pl.d = prm->d;
-    pl.kernel = prm->kernel;
+    pl.kernel = kern_of(prm->kernel);
     pl.rec_bytes = (size_t)4 * (prm->d + 1);
     if (pl.n <= RBM_SINGLE_CAP) {
         pl.nbuck = pl.nb1 = 1;
@@ -186,6 +198,7 @@ StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m, bool pendi
     s.ssd = (float)(prm->sigma * std::sqrt(prm->dt));
     s.pm = m - 1u;
     s.pssd = pending ? s.ssd : 0.0f;
+    s.split = prm->kernel == RBM_K_COULOMB_SPLIT ? 1u : 0u;
     return s;
 }
 
@@ -562,7 +575,7 @@ rbm_status direct_forces(const rbm_params *prm, const float *d_x, const uint32_t
     if (nids == 0) return RBM_OK;
     const Plan pl = make_plan(prm);
     const StepArgs s = make_args(prm, pl, 0, false);
-    hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, d_ids, (uint32_t)nids, d_f, 0,
+    hipError_t e = rbm::launch_direct(s, prm->d, kern_of(prm->kernel), d_x, d_ids, (uint32_t)nids, d_f, 0,
                                       (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_forces launch");
 }
@@ -579,7 +592,7 @@ rbm_status direct_moments(const rbm_params *prm, const float *d_x, const uint32_
     if (nids == 0) return RBM_OK;
     const Plan pl = make_plan(prm);
     const StepArgs s = make_args(prm, pl, 0, false);
-    hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, d_ids, (uint32_t)nids, d_f, 0,
+    hipError_t e = rbm::launch_direct(s, prm->d, kern_of(prm->kernel), d_x, d_ids, (uint32_t)nids, d_f, 0,
                                       (hipStream_t)stream, d_m2);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_moments launch");
 }
@@ -595,7 +608,7 @@ rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out, 
     if (step < 0 || step > 0xffffffffLL) return fail(RBM_ERR_INVALID, "step out of range");
     const Plan pl = make_plan(prm);
     const StepArgs s = make_args(prm, pl, (uint32_t)step, false);
-    hipError_t e = rbm::launch_direct(s, prm->d, prm->kernel, d_x, nullptr, (uint32_t)prm->n,
+    hipError_t e = rbm::launch_direct(s, prm->d, kern_of(prm->kernel), d_x, nullptr, (uint32_t)prm->n,
                                       d_x_out, 1, (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "direct_step launch");
 }

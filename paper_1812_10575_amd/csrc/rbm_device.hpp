@@ -137,7 +137,29 @@ struct StepArgs {
     float ssd;       // sigma * sqrt(dt)
     uint32_t pm;     // step whose noise the stored positions still lack
     float pssd;      // its amplitude (0: none pending)
+    uint32_t split;  // 1: batches of two move by the exact pair flow of K(x) = x/|x|^2
 };
+
+// Exact flow over a time dt of a batch of two particles under
+// K(x) = x/|x|^2 (Sec. 2.3 splitting for singular K, the scheme of Sec. 4.2):
+// the centre c = (xi + xj)/2 stays, u = xi - xj keeps its direction and
+// |u|^2 grows by 4 dt, so yi = c + g u/2 with g = sqrt(1 + 4 dt/|u|^2).
+// Written for one member; the partner's call (with the arguments swapped)
+// gives c - g u/2 with the same roundings.  u = 0 stays at c.
+template <int D>
+__device__ __forceinline__ void pair_flow(float dt, const float (&xi)[D], const float *xj, float (&yi)[D])
+{
+    float c[D], u[D], r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        c[k] = 0.5f * (xi[k] + xj[k]);
+        u[k] = xi[k] - xj[k];
+        r2 = fmaf(u[k], u[k], r2);
+    }
+    const float h = r2 > 0.0f ? 0.5f * sqrtf(fmaf(4.0f * dt, __builtin_amdgcn_rcpf(r2), 1.0f)) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) yi[k] = fmaf(h, u[k], c[k]);
+}
 
 // Batch [bs, be) of sorted rank r: groups of p, the last also takes the
 // n mod p leftover ranks.

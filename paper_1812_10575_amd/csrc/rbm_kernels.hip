@@ -437,6 +437,17 @@ __device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, u
         }
         id[i] = r.id;
     }
+    if constexpr (P == 2) {
+        if (s.split && !fout) {
+            // the pair moves by its exact flow, then the external field acts
+            float y[2][D], zero[D] = {};
+            pair_flow<D>(s.dt, x[0], x[1], y[0]);
+            pair_flow<D>(s.dt, x[1], x[0], y[1]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) finish<D>(s, y[i], zero, id[i], bs + i, dst, fout);
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
 #pragma unroll
@@ -690,7 +701,21 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
     const uint32_t tid = threadIdx.x;
     if (tid < sz) sh[tid] = dst[bs + tid];
     __syncthreads();
-    if (tid < sz) {
+    if (tid < sz && s.split && !fout && sz == 2) {
+        // a pair moves by its exact flow (the same operations as in the sort kernel)
+        const Rec<D> me = sh[tid];
+        float xi[D], y[D];
+        const float zero[D] = {};
+#pragma unroll
+        for (int c = 0; c < D; ++c) xi[c] = me.x[c];
+        pair_flow<D>(s.dt, xi, sh[1 - tid].x, y);
+        drift_update<D>(s, y, zero);
+        Rec<D> o;
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.x[c] = y[c];
+        o.id = me.id;
+        dst[bs + tid] = o;
+    } else if (tid < sz) {
         const Rec<D> me = sh[tid];
         float xi[D], f[D];
 #pragma unroll

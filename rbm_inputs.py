@@ -58,6 +58,8 @@ def workload(name: str, n: int, seed: int = 1) -> np.ndarray:
         return normal(n, 3, seed)
     if name == "semicircle":
         return semicircle(n, 2.0, seed)
+    if name == "semicircle2":  # radius 2: the analytic density of Sec. 4.2 at t = 0
+        return semicircle(n, 2.0, seed)
     raise ValueError(f"unknown workload {name!r}")
 
 
@@ -71,6 +73,10 @@ WORKLOADS = {
     # 1-D softened Coulomb (eps = 1e-3) in a harmonic trap, no noise
     "dyson1d-n2^20-p2": dict(d=1, kernel=1, n=1 << 20, p=2, kparam=1e-6, beta=1.0, sigma=0.0,
                              dt=1e-4, seed=1, init="dyson1d", steps=100000),
+    # 1-D Dyson Brownian motion (K = 1/x, V = x^2/2, sigma = 1/sqrt(N)) by the
+    # splitting with the exact pair flow, from the radius-2 semicircle
+    "dysonsplit1d-n2^20-p2": dict(d=1, kernel=3, n=1 << 20, p=2, kparam=0.0, beta=1.0,
+                                  sigma=1.0 / 1024.0, dt=1e-3, seed=1, init="semicircle2", steps=5000),
     # the Gaussian workload at 2^22 particles (control-variate comparison)
     "gauss2d-n2^22-p2": dict(d=2, kernel=0, n=1 << 22, p=2, kparam=0.0, beta=1.0, sigma=0.5,
                              dt=1e-3, seed=1, init="gauss2d", steps=1000),

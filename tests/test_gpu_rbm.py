@@ -310,3 +310,63 @@ def test_dyson1d_relaxes_to_the_semicircle():
     say(f"KS={ks:.5f} m2={m2:.5f} m2*={m2s:.5f}")
     assert ks <= 0.01
     assert abs(m2 - m2s) < 0.01
+
+
+# --------------------------------------------------------------------------
+# splitting with the exact pair flow (K = x/|x|^2, p = 2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d", [(1024, 1), (20000, 1), (300002, 1), (50000, 2), (4096, 3)])
+def test_split_scheme_matches_the_oracle(n, d):
+    """Permutation bit-exact and e1 <= 1e-5 for three steps, forces of the
+    division against the oracle's x/|x|^2 forces."""
+    w = rbm_inputs.params_of("dysonsplit1d-n2^20-p2", n=n, d=d, sigma=1.0 / math.sqrt(n))
+    w["init"] = "semicircle2" if d == 1 else "gauss2d" if d == 2 else "attrep3d"
+    say("split", n, d)
+    ctx, _ = start(w)
+    o = op(w)
+    for m in range(3):
+        xm, sm = state(ctx)
+        rbm.rbm_step(ctx)
+        x1, s1 = state(ctx)
+        xo, so = ora.rbm_step(o, 2, m, xm.astype(np.float64), sm)
+        assert np.array_equal(s1, so), m
+        assert e_rel(x1, xo) <= 1e-5, (m, e_rel(x1, xo))
+    rbm.rbm_check(ctx)
+    x, s = state(ctx)
+    f = rbm.rbm_forces(ctx, 3).cpu().numpy()
+    fo = ora.rbm_forces(o, 2, x.astype(np.float64), ora.permutation(o, 3, s))
+    assert e_rel(f, fo) <= 1e-5
+
+
+def test_split_scheme_hundred_steps():
+    w = rbm_inputs.params_of("dysonsplit1d-n2^20-p2", n=20000, sigma=1.0 / math.sqrt(20000))
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, 100)
+    x1, s1 = state(ctx)
+    xo, so = ora.rbm_run(op(w), 2, 0, 100, x0.astype(np.float64))
+    assert np.array_equal(s1, so)
+    assert e_rel(x1, xo) <= 1e-3
+
+
+def test_dyson_split_follows_the_analytic_density_at_scale():
+    """Sec. 4.2 at N = 2^20: from the radius-2 semicircle the empirical law
+    follows rho(x, t) = sqrt(2 s(t) - x^2) / (s(t) pi), s(t) = 1 + e^{-2t}
+    (KS <= 0.01 and second moment s(t)/2 at t = 0.5, 1 and 5), ending at the
+    semicircle of radius sqrt(2) without the bias of the softened Euler
+    scheme."""
+    w = rbm_inputs.params_of("dysonsplit1d-n2^20-p2")
+    ctx, _ = start(w)
+    m = 0
+    for t_end in (0.5, 1.0, 5.0):
+        steps = int(round(t_end / w["dt"])) - m
+        rbm.rbm_run(ctx, steps)
+        m += steps
+        x, _ = state(ctx)
+        sig = 1 + math.exp(-2 * t_end)
+        ks = ora.ks_distance(x[:, 0].astype(np.float64), lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig)))
+        m2 = float(np.mean(x.astype(np.float64) ** 2))
+        say("t", t_end, "KS", ks, "m2", m2, "analytic", sig / 2)
+        assert ks <= 0.01, (t_end, ks)
+        assert abs(m2 - sig / 2) <= 0.003, (t_end, m2)
+    rbm.rbm_check(ctx)
