@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT = 0, 1, 2, 3
+K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT, K_WEALTH_SPLIT = 0, 1, 2, 3, 4
 
 
 class _Params(ctypes.Structure):
@@ -74,6 +74,8 @@ def _load():
     lib.ora_direct_forces.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p]
     lib.ora_direct_moments.argtypes = [pp, ctypes.c_int64, f64p, u32p, ctypes.c_int64, f64p, f64p]
     lib.ora_pair_flow.argtypes = [ctypes.c_int32, ctypes.c_double, f64p, f64p, f64p, f64p]
+    lib.ora_pair_flow_linear.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, f64p, f64p, f64p,
+                                         f64p]
     lib.ora_rbm_step.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, f64p, u32p]
     lib.ora_rbm_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_int64, f64p, u32p]
@@ -221,6 +223,29 @@ def pair_flow(d: int, t: float, xi, xj):
     _load().ora_pair_flow(d, t, _p(a, ctypes.c_double), _p(b, ctypes.c_double), _p(yi, ctypes.c_double),
                           _p(yj, ctypes.c_double))
     return yi, yj
+
+
+def pair_flow_linear(d: int, t: float, kappa: float, xi, xj):
+    """Exact flow over time t of a pair under K(x) = -kappa x (Sec. 5):
+    returns (yi, yj)."""
+    a, b = _f64(xi).copy(), _f64(xj).copy()
+    yi, yj = np.zeros(d), np.zeros(d)
+    _load().ora_pair_flow_linear(d, t, kappa, _p(a, ctypes.c_double), _p(b, ctypes.c_double),
+                                 _p(yi, ctypes.c_double), _p(yj, ctypes.c_double))
+    return yi, yj
+
+
+def inverse_gamma_cdf(y, shape, scale):
+    """CDF of the inverse Gamma law rho(y) = scale^shape / Gamma(shape)
+    y^-(shape+1) e^(-scale/y), y > 0: the equilibrium of the wealth model of
+    Sec. 5 has shape kappa/D + 1 and scale kappa eta / D (eta the mean
+    wealth)."""
+    from scipy.special import gammaincc
+    y = np.asarray(y, np.float64)
+    out = np.zeros_like(y)
+    pos = y > 0
+    out[pos] = gammaincc(shape, scale / y[pos])
+    return out
 
 
 def semicircle_cdf_r(x, radius):

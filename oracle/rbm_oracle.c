@@ -129,7 +129,8 @@ void ora_normals(uint64_t seed, uint32_t sys, uint32_t m, uint32_t id, double z[
 /* Model: the pair kernel K and the external field -grad V of eq. (1.2)     */
 /* ------------------------------------------------------------------------ */
 
-enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2, ORA_K_COULOMB_SPLIT = 3 };
+enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2, ORA_K_COULOMB_SPLIT = 3,
+       ORA_K_WEALTH_SPLIT = 4 };
 
 typedef struct {
     int32_t d;          /* space dimension, 1..3 */
@@ -149,6 +150,9 @@ typedef struct {
  *   ATTREP      K(x) = x / (|x|^2 + a) - x
  *   COULOMB_SPLIT K(x) = x / |x|^2, the singular kernel of Sec. 4.2, whose
  *               steps use the splitting with the exact pair flow (below)
+ *   WEALTH_SPLIT  K(x) = -a x, the trading interaction phi(y) = y^2/2 of the
+ *               wealth model of Sec. 5 (a = kappa), stepped by splitting:
+ *               exact pair flow, then exact multiplicative noise (below)
  * All are odd: K(-x) = -K(x). */
 void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, double *out)
 {
@@ -160,6 +164,7 @@ void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, doubl
     case ORA_K_SOFTCOULOMB: s = 1.0 / (r2 + a); break;
     case ORA_K_ATTREP:      s = 1.0 / (r2 + a) - 1.0; break;
     case ORA_K_COULOMB_SPLIT: s = 1.0 / r2; break;
+    case ORA_K_WEALTH_SPLIT: s = -a; break;
     default:                s = 0.0; break;
     }
     for (int k = 0; k < d; ++k) out[k] = s * x[k];
@@ -322,12 +327,47 @@ void ora_pair_flow(int32_t d, double t, const double *xi, const double *xj, doub
     }
 }
 
+/* Exact flow over a time t of a batch of two particles under K(x) = -kappa x
+ * (prefactor 1/(p-1) = 1): the pair's mean c stays and u = xi - xj obeys
+ * du/dt = -2 kappa u, so yi = c + e^{-2 kappa t} u/2, yj = c - e^{-2 kappa t} u/2
+ * (the interaction part of the mean-preserving splitting of Sec. 5). */
+void ora_pair_flow_linear(int32_t d, double t, double kappa, const double *xi, const double *xj,
+                          double *yi, double *yj)
+{
+    const double g = exp(-2.0 * kappa * t);
+    for (int k = 0; k < d; ++k) {
+        const double c = 0.5 * (xi[k] + xj[k]), u = xi[k] - xj[k];
+        yi[k] = c + 0.5 * g * u;
+        yj[k] = c - 0.5 * g * u;
+    }
+}
+
+/* The noise part of the wealth model's splitting: dY = sigma Y dB (sigma =
+ * sqrt(2D)) solved exactly over dt, Y <- Y exp(sigma sqrt(dt) z - sigma^2
+ * dt / 2), after the field step Y <- Y - dt beta Y.  The factor has mean 1,
+ * so the mean wealth is kept in expectation (the pair step keeps it
+ * exactly). */
+static void gbm_update(const ora_params *prm, int64_t n, uint32_t m, double *x)
+{
+    const int d = prm->d;
+    const double sq = sqrt(prm->dt), s = prm->sigma;
+    for (int64_t i = 0; i < n; ++i) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (s != 0.0) ora_normals(prm->seed, prm->sys, m, (uint32_t)i, z);
+        for (int k = 0; k < d; ++k) {
+            const double y = x[i * d + k] + prm->dt * (-prm->beta * x[i * d + k]);
+            x[i * d + k] = y * exp(s * sq * z[k] - 0.5 * s * s * prm->dt);
+        }
+    }
+}
+
 /* One RBM-1 step m (Algorithm 1): draw the division from the slot order,
  * compute batch forces at the old positions, update.  slots is replaced by
  * the new order (the sorted permutation).  COULOMB_SPLIT (p = 2, N even):
  * each pair moves by its exact flow over dt, then the external field and
  * the noise act by one Euler-Maruyama step from the moved positions
- * (Sec. 2.3 splitting, Sec. 4.2). */
+ * (Sec. 2.3 splitting, Sec. 4.2).  WEALTH_SPLIT (p = 2, N even): the pair
+ * flow of K = -kappa x, then the exact multiplicative noise (Sec. 5). */
 void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
                   double *x, uint32_t *slots)
 {
@@ -345,6 +385,19 @@ void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
             }
         }
         for (int64_t e = 0; e < n * d; ++e) f[e] = 0.0;
+    } else if (prm->kernel == ORA_K_WEALTH_SPLIT) {
+        for (int64_t q = 0; q + 1 < n; q += 2) {
+            const int64_t i = slots[q], j = slots[q + 1];
+            double yi[3], yj[3];
+            ora_pair_flow_linear(d, prm->dt, prm->kparam, x + i * d, x + j * d, yi, yj);
+            for (int k = 0; k < d; ++k) {
+                x[i * d + k] = yi[k];
+                x[j * d + k] = yj[k];
+            }
+        }
+        gbm_update(prm, n, m, x);
+        free(f);
+        return;
     } else {
         ora_rbm_forces(prm, n, p, x, slots, f);
     }

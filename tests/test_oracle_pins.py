@@ -500,3 +500,64 @@ def test_dyson_split_follows_the_analytic_density(ora):
         ks = ora.ks_distance(x[:, 0], lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig)))
         assert ks < 0.02, (t_end, ks)
         assert np.mean(x ** 2) == pytest.approx(sig / 2, abs=0.01), t_end
+
+
+# --------------------------------------------------------------------------
+# the wealth model of Sec. 5: linear trading kernel, multiplicative noise
+# --------------------------------------------------------------------------
+
+def test_linear_pair_flow_is_exact(ora):
+    """Pair flow of K = -kappa x: RK4 of the pair ODE, the pair's mean kept,
+    composition of two flows."""
+    rng = np.random.default_rng(7)
+    for d in (1, 2):
+        xi, xj = rng.standard_normal(d), rng.standard_normal(d)
+        kappa, t = 1.3, 0.4
+        yi, yj = ora.pair_flow_linear(d, t, kappa, xi, xj)
+        y = np.concatenate([xi, xj])
+        h = t / 4000
+        rhs = lambda v: np.concatenate([-kappa * (v[:d] - v[d:]), -kappa * (v[d:] - v[:d])])
+        for _ in range(4000):
+            k1 = rhs(y); k2 = rhs(y + 0.5 * h * k1); k3 = rhs(y + 0.5 * h * k2); k4 = rhs(y + h * k3)
+            y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        np.testing.assert_allclose(np.concatenate([yi, yj]), y, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(yi + yj, xi + xj, atol=1e-15)
+        ai, aj = ora.pair_flow_linear(d, 0.1, kappa, xi, xj)
+        bi, bj = ora.pair_flow_linear(d, 0.3, kappa, ai, aj)
+        np.testing.assert_allclose(bi, yi, atol=1e-15)
+
+
+def test_wealth_noise_is_the_exact_geometric_brownian_factor(ora):
+    """Equal wealths do not trade, so one step multiplies each by
+    exp(sigma sqrt(dt) z - sigma^2 dt / 2): log-normal with the right
+    parameters, mean 1."""
+    n, sigma, dt = 1 << 16, math.sqrt(2.0), 0.01
+    prm = ora.Params(d=1, kernel=ora.K_WEALTH_SPLIT, kparam=1.0, beta=0.0, sigma=sigma, dt=dt, seed=9)
+    x1, _ = ora.rbm_step(prm, 2, 4, np.ones((n, 1)), np.arange(n))
+    from scipy import stats
+    lg = np.log(x1[:, 0])
+    assert stats.kstest(lg, "norm", args=(-0.5 * sigma * sigma * dt, sigma * math.sqrt(dt))).pvalue > 1e-3
+    assert np.mean(x1) == pytest.approx(1.0, abs=4 * sigma * math.sqrt(dt) / math.sqrt(n))
+
+
+def test_inverse_gamma_cdf_closed_form(ora):
+    """Shape 2: F(y) = (1 + s/y) e^(-s/y); density by differences."""
+    y = np.linspace(0.05, 20, 400)
+    s = 0.8
+    np.testing.assert_allclose(ora.inverse_gamma_cdf(y, 2.0, s), (1 + s / y) * np.exp(-s / y), rtol=1e-13)
+    h = 1e-6
+    dens = (ora.inverse_gamma_cdf(y + h, 2.0, s) - ora.inverse_gamma_cdf(y - h, 2.0, s)) / (2 * h)
+    np.testing.assert_allclose(dens, s * s * y ** -3 * np.exp(-s / y), rtol=1e-6)
+
+
+def test_wealth_reaches_the_inverse_gamma_equilibrium(ora):
+    """Sec. 5 with kappa = D = 1 (sigma = sqrt 2), tau = 1e-3, T = 3, wealth
+    started at |N(0,1)|: the empirical law is the inverse Gamma law of shape
+    kappa/D + 1 = 2 and scale kappa eta / D, eta the mean wealth."""
+    n = 8192
+    prm = ora.Params(d=1, kernel=ora.K_WEALTH_SPLIT, kparam=1.0, beta=0.0, sigma=math.sqrt(2.0), dt=1e-3, seed=3)
+    x = np.abs(rbm_inputs.normal(n, 1, seed=5).astype(np.float64))
+    x1, _ = ora.rbm_run(prm, 2, 0, 3000, x)
+    eta = float(x1.mean())
+    assert ora.ks_distance(x1[:, 0], lambda v: ora.inverse_gamma_cdf(v, 2.0, eta)) < 0.03
+    assert np.all(x1 > 0)
