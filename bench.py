@@ -287,6 +287,33 @@ def dyson_split(args) -> dict:
             "ks_vs_analytic": ks, "m2": float(np.mean(x * x)), "m2_analytic": sig / 2}
 
 
+def wealth(args) -> dict:
+    """Sec. 5's wealth model (kappa = D = 1, quadratic trading, p = 2, exact
+    pair flow and exact multiplicative noise, tau = 1e-3), N = 2^20 from
+    |N(0,1)| to T = 3: throughput and the KS distance to the inverse Gamma
+    law of shape 2 and scale the mean wealth."""
+    import numpy as np
+    import torch
+    import oracle as ora
+    import paper_1812_10575_amd as rbm
+    import rbm_inputs
+    w = rbm_inputs.params_of("wealth1d-n2^20-p2")
+    prm = rbm.Params(**{k: w[k] for k in FIELDS})
+    ctx = rbm.rbm_init(prm, torch.from_numpy(rbm_inputs.workload(w["init"], w["n"], w["seed"])).cuda())
+    rbm.rbm_run(ctx, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbm.rbm_run(ctx, w["steps"] - 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rbm.rbm_check(ctx)
+    y = rbm.rbm_positions(ctx).cpu().numpy()[:, 0].astype(np.float64)
+    eta = float(y.mean())
+    return {"workload": "wealth1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": w["steps"] * w["dt"],
+            "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
+            "mean_wealth": eta, "ks_vs_inverse_gamma": ora.ks_distance(y, lambda v: ora.inverse_gamma_cdf(v, 2.0, eta))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,6 +424,7 @@ def main() -> int:
         out["ensemble"] = ensemble_rate(args)
     if not args.no_sweep:
         out["dyson_split"] = dyson_split(args)
+        out["wealth"] = wealth(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

@@ -59,12 +59,20 @@ typedef enum {
  *                     by its exact flow over dt (centre fixed, direction kept,
  *                     |X^i - X^j|^2 grows by 4 dt: the scheme of Sec. 4.2 for the
  *                     Dyson Brownian motion), then X += -dt beta X + sigma sqrt(dt) z.
- *                     Forces (rbm_forces, direct_*) are those of x/|x|^2.     */
+ *                     Forces (rbm_forces, direct_*) are those of x/|x|^2.
+ *   RBM_K_WEALTH_SPLIT  K(x) = -a x (a = kappa > 0, the trading interaction
+ *                     phi(y) = y^2/2 of the wealth model of Sec. 5), p = 2 (N
+ *                     even): each pair moves by its exact flow (mean kept,
+ *                     difference times e^{-2 a dt}), then X += -dt beta X and
+ *                     the exact multiplicative noise of dX = sigma X dB,
+ *                     X *= exp(sigma sqrt(dt) z - sigma^2 dt / 2) (sigma =
+ *                     sqrt(2D)).  direct_step does not take this kernel.     */
 typedef enum {
     RBM_K_GAUSS = 0,
     RBM_K_SOFTCOULOMB = 1,
     RBM_K_ATTREP = 2,
-    RBM_K_COULOMB_SPLIT = 3
+    RBM_K_COULOMB_SPLIT = 3,
+    RBM_K_WEALTH_SPLIT = 4
 } rbm_kernel;
 
 /* Model, method and stream parameters.  V(x) = beta |x|^2 / 2. */

@@ -31,7 +31,7 @@ SYMBOLS = (
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
-RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT = 0, 1, 2, 3
+RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT, RBM_K_WEALTH_SPLIT = 0, 1, 2, 3, 4
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
 

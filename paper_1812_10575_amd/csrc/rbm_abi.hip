@@ -66,8 +66,10 @@ rbm_status check_params(const rbm_params *prm)
 {
     if (!prm) return fail(RBM_ERR_INVALID, "params is NULL");
     if (prm->d < 1 || prm->d > 3) return fail(RBM_ERR_INVALID, "d = %d not in 1..3", prm->d);
-    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_COULOMB_SPLIT)
+    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_WEALTH_SPLIT)
         return fail(RBM_ERR_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == RBM_K_WEALTH_SPLIT && !(prm->kparam > 0.0))
+        return fail(RBM_ERR_INVALID, "the wealth model needs a trading rate kparam > 0");
     if (prm->kernel == RBM_K_COULOMB_SPLIT && prm->kparam != 0.0)
         return fail(RBM_ERR_INVALID, "the split Coulomb kernel has no softening (kparam must be 0)");
     if (prm->n < 2) return fail(RBM_ERR_INVALID, "N = %lld < 2", (long long)prm->n);
@@ -87,7 +89,8 @@ rbm_status check_params(const rbm_params *prm)
     if (!(prm->kparam >= 0.0) || !std::isfinite(prm->kparam))
         return fail(RBM_ERR_INVALID, "kparam must be >= 0");
     if (!std::isfinite(prm->beta)) return fail(RBM_ERR_INVALID, "beta must be finite");
-    if (prm->kernel == RBM_K_COULOMB_SPLIT && (prm->p != 2 || prm->n % 2 != 0))
+    if ((prm->kernel == RBM_K_COULOMB_SPLIT || prm->kernel == RBM_K_WEALTH_SPLIT) &&
+        (prm->p != 2 || prm->n % 2 != 0))
         return fail(RBM_ERR_UNSUPPORTED, "the exact pair flow needs p = 2 and an even N");
     if (prm->n > RBM_SINGLE_CAP && prm->p > RBM_MAX_P_MULTI)
         return fail(RBM_ERR_UNSUPPORTED, "p = %d above %d needs N <= %d", prm->p, RBM_MAX_P_MULTI,
@@ -97,10 +100,13 @@ rbm_status check_params(const rbm_params *prm)
 
 // The force kernel of the kernels: the split Coulomb kernel evaluates its
 // forces (rbm_forces, the direct sum) as x/|x|^2, the soft Coulomb kernel
-// with a = 0; its steps differ by StepArgs.split.
+// with a = 0, the wealth model as -a x; their steps differ by
+// StepArgs.scheme.
 int kern_of(int kernel)
 {
-    return kernel == RBM_K_COULOMB_SPLIT ? RBM_K_SOFTCOULOMB : kernel;
+    if (kernel == RBM_K_COULOMB_SPLIT) return rbm::K_SOFTCOULOMB;
+    if (kernel == RBM_K_WEALTH_SPLIT) return rbm::K_LINEAR;
+    return kernel;
 }
 
 Plan make_plan(const rbm_params *prm)
@@ -198,7 +204,8 @@ StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m, bool pendi
     s.ssd = (float)(prm->sigma * std::sqrt(prm->dt));
     s.pm = m - 1u;
     s.pssd = pending ? s.ssd : 0.0f;
-    s.split = prm->kernel == RBM_K_COULOMB_SPLIT ? 1u : 0u;
+    s.scheme = prm->kernel == RBM_K_COULOMB_SPLIT ? 1u : prm->kernel == RBM_K_WEALTH_SPLIT ? 2u : 0u;
+    s.flowc = (float)std::exp(-2.0 * prm->kparam * prm->dt);
     return s;
 }
 
@@ -603,6 +610,8 @@ rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out, 
     rbm_status st = check_params(prm);
     if (st == RBM_ERR_UNSUPPORTED && prm && prm->n <= RBM_MAX_N) st = RBM_OK;
     if (st != RBM_OK) return st;
+    if (prm->kernel == RBM_K_WEALTH_SPLIT)
+        return fail(RBM_ERR_UNSUPPORTED, "direct_step has additive noise; the wealth model's is multiplicative");
     if (!d_x || !d_x_out) return fail(RBM_ERR_INVALID, "NULL pointer argument");
     if (d_x == d_x_out) return fail(RBM_ERR_INVALID, "d_x_out must not alias d_x");
     if (step < 0 || step > 0xffffffffLL) return fail(RBM_ERR_INVALID, "step out of range");

@@ -89,7 +89,7 @@ template <> struct alignas(16) Rec<3> { float x[3]; uint32_t id; };
 //   SOFTCOULOMB s = 1 / (r2 + a)
 //   ATTREP      s = 1 / (r2 + a) - 1
 // ---------------------------------------------------------------------------
-enum : int { K_GAUSS = 0, K_SOFTCOULOMB = 1, K_ATTREP = 2 };
+enum : int { K_GAUSS = 0, K_SOFTCOULOMB = 1, K_ATTREP = 2, K_LINEAR = 3 };
 
 template <int KERN>
 __device__ __forceinline__ float pair_scale(float r2, float a)
@@ -98,6 +98,8 @@ __device__ __forceinline__ float pair_scale(float r2, float a)
         return -__builtin_amdgcn_exp2f(-1.4426950408889634f * r2);  // -e^{-r2}
     } else if constexpr (KERN == K_SOFTCOULOMB) {
         return __builtin_amdgcn_rcpf(r2 + a);
+    } else if constexpr (KERN == K_LINEAR) {
+        return -a;  // K(x) = -a x
     } else {
         return __builtin_amdgcn_rcpf(r2 + a) - 1.0f;
     }
@@ -137,8 +139,22 @@ struct StepArgs {
     float ssd;       // sigma * sqrt(dt)
     uint32_t pm;     // step whose noise the stored positions still lack
     float pssd;      // its amplitude (0: none pending)
-    uint32_t split;  // 1: batches of two move by the exact pair flow of K(x) = x/|x|^2
+    uint32_t scheme; // 0: Euler-Maruyama; batches of two move by their exact pair flow,
+                     // 1: of K(x) = x/|x|^2 (additive noise), 2: of K(x) = -a x, with
+                     //    multiplicative noise x <- x exp(sigma sqrt(dt) z - sigma^2 dt / 2)
+    float flowc;     // scheme 2: e^{-2 a dt}, the decay of a pair's difference over a step
 };
+
+// Exact flow over a step of a batch of two particles under K(x) = -a x (the
+// trading interaction of the wealth model, Sec. 5): the pair's mean stays
+// and the difference decays by flowc = e^{-2 a dt}; written for one member,
+// like pair_flow.
+template <int D>
+__device__ __forceinline__ void pair_flow_linear(float flowc, const float (&xi)[D], const float *xj, float (&yi)[D])
+{
+#pragma unroll
+    for (int k = 0; k < D; ++k) yi[k] = fmaf(0.5f * flowc, xi[k] - xj[k], 0.5f * (xi[k] + xj[k]));
+}
 
 // Exact flow over a time dt of a batch of two particles under
 // K(x) = x/|x|^2 (Sec. 2.3 splitting for singular K, the scheme of Sec. 4.2):
@@ -190,8 +206,15 @@ __device__ __forceinline__ void add_pending_noise(const StepArgs &s, float *x, u
     if (s.pssd != 0.0f) {
         float z[D];
         noise<D>(id, s.pm, s.sys, s.k0, s.k1, z);
+        if (s.scheme == 2) {
+            // the exact factor of dY = sigma Y dB over the step
+            const float h = -0.5f * s.pssd * s.pssd;
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = fmaf(s.pssd, z[k], x[k]);
+            for (int k = 0; k < D; ++k) x[k] = x[k] * expf(fmaf(s.pssd, z[k], h));
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[k] = fmaf(s.pssd, z[k], x[k]);
+        }
     }
 }
 

@@ -438,11 +438,16 @@ __device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, u
         id[i] = r.id;
     }
     if constexpr (P == 2) {
-        if (s.split && !fout) {
+        if (s.scheme != 0 && !fout) {
             // the pair moves by its exact flow, then the external field acts
             float y[2][D], zero[D] = {};
-            pair_flow<D>(s.dt, x[0], x[1], y[0]);
-            pair_flow<D>(s.dt, x[1], x[0], y[1]);
+            if (s.scheme == 1) {
+                pair_flow<D>(s.dt, x[0], x[1], y[0]);
+                pair_flow<D>(s.dt, x[1], x[0], y[1]);
+            } else {
+                pair_flow_linear<D>(s.flowc, x[0], x[1], y[0]);
+                pair_flow_linear<D>(s.flowc, x[1], x[0], y[1]);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i) finish<D>(s, y[i], zero, id[i], bs + i, dst, fout);
             return;
@@ -701,14 +706,17 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
     const uint32_t tid = threadIdx.x;
     if (tid < sz) sh[tid] = dst[bs + tid];
     __syncthreads();
-    if (tid < sz && s.split && !fout && sz == 2) {
+    if (tid < sz && s.scheme != 0 && !fout && sz == 2) {
         // a pair moves by its exact flow (the same operations as in the sort kernel)
         const Rec<D> me = sh[tid];
         float xi[D], y[D];
         const float zero[D] = {};
 #pragma unroll
         for (int c = 0; c < D; ++c) xi[c] = me.x[c];
-        pair_flow<D>(s.dt, xi, sh[1 - tid].x, y);
+        if (s.scheme == 1)
+            pair_flow<D>(s.dt, xi, sh[1 - tid].x, y);
+        else
+            pair_flow_linear<D>(s.flowc, xi, sh[1 - tid].x, y);
         drift_update<D>(s, y, zero);
         Rec<D> o;
 #pragma unroll
@@ -1113,6 +1121,7 @@ hipError_t step_d(const Plan &pl, const StepArgs &s, int kernel, void *ws, hipSt
     switch (kernel) {
     case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    case K_LINEAR: return step_dk<D, K_LINEAR>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     }
 }
@@ -1138,6 +1147,7 @@ hipError_t direct_d(const StepArgs &s, int kernel, const float *x, const uint32_
     switch (kernel) {
     case K_GAUSS: return direct_dk<D, K_GAUSS>(s, x, ids, nids, out, step, m2, st);
     case K_SOFTCOULOMB: return direct_dk<D, K_SOFTCOULOMB>(s, x, ids, nids, out, step, m2, st);
+    case K_LINEAR: return direct_dk<D, K_LINEAR>(s, x, ids, nids, out, step, m2, st);
     default: return direct_dk<D, K_ATTREP>(s, x, ids, nids, out, step, m2, st);
     }
 }

@@ -60,6 +60,8 @@ def workload(name: str, n: int, seed: int = 1) -> np.ndarray:
         return semicircle(n, 2.0, seed)
     if name == "semicircle2":  # radius 2: the analytic density of Sec. 4.2 at t = 0
         return semicircle(n, 2.0, seed)
+    if name == "absnormal":  # initial wealth |N(0, 1)| (Sec. 5)
+        return np.abs(normal(n, 1, seed))
     raise ValueError(f"unknown workload {name!r}")
 
 
@@ -77,6 +79,10 @@ WORKLOADS = {
     # splitting with the exact pair flow, from the radius-2 semicircle
     "dysonsplit1d-n2^20-p2": dict(d=1, kernel=3, n=1 << 20, p=2, kparam=0.0, beta=1.0,
                                   sigma=1.0 / 1024.0, dt=1e-3, seed=1, init="semicircle2", steps=5000),
+    # wealth model of Sec. 5: kappa = D = 1 (sigma = sqrt 2), quadratic trading,
+    # pair flow and exact multiplicative noise, wealth started at |N(0, 1)|
+    "wealth1d-n2^20-p2": dict(d=1, kernel=4, n=1 << 20, p=2, kparam=1.0, beta=0.0, sigma=2.0 ** 0.5,
+                              dt=1e-3, seed=1, init="absnormal", steps=3000),
     # the Gaussian workload at 2^22 particles (control-variate comparison)
     "gauss2d-n2^22-p2": dict(d=2, kernel=0, n=1 << 22, p=2, kparam=0.0, beta=1.0, sigma=0.5,
                              dt=1e-3, seed=1, init="gauss2d", steps=1000),

@@ -370,3 +370,58 @@ def test_dyson_split_follows_the_analytic_density_at_scale():
         assert ks <= 0.01, (t_end, ks)
         assert abs(m2 - sig / 2) <= 0.003, (t_end, m2)
     rbm.rbm_check(ctx)
+
+
+# --------------------------------------------------------------------------
+# the wealth model (linear trading kernel, exact pair flow, multiplicative noise)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1024, 20000, 300002])
+def test_wealth_scheme_matches_the_oracle(n):
+    w = rbm_inputs.params_of("wealth1d-n2^20-p2", n=n)
+    say("wealth", n)
+    ctx, _ = start(w)
+    o = op(w)
+    for m in range(3):
+        xm, sm = state(ctx)
+        rbm.rbm_step(ctx)
+        x1, s1 = state(ctx)
+        xo, so = ora.rbm_step(o, 2, m, xm.astype(np.float64), sm)
+        assert np.array_equal(s1, so), m
+        assert e_rel(x1, xo) <= 1e-5, (m, e_rel(x1, xo))
+    rbm.rbm_check(ctx)
+    x, s = state(ctx)
+    f = rbm.rbm_forces(ctx, 3).cpu().numpy()
+    fo = ora.rbm_forces(o, 2, x.astype(np.float64), ora.permutation(o, 3, s))
+    assert e_rel(f, fo) <= 1e-5
+    with pytest.raises(rbm.RbmError):
+        rbm.direct_step(gp(w), torch.from_numpy(np.ascontiguousarray(x)).cuda(), 0)
+
+
+def test_wealth_scheme_hundred_steps():
+    w = rbm_inputs.params_of("wealth1d-n2^20-p2", n=20000)
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, 100)
+    x1, s1 = state(ctx)
+    xo, so = ora.rbm_run(op(w), 2, 0, 100, x0.astype(np.float64))
+    assert np.array_equal(s1, so)
+    assert e_rel(x1, xo) <= 1e-3
+
+
+def test_wealth_reaches_the_inverse_gamma_law_at_scale():
+    """Sec. 5 at N = 2^20, kappa = D = 1, tau = 1e-3, T = 3, from |N(0,1)|:
+    every wealth stays positive, the mean wealth stays at sqrt(2/pi) up to
+    the noise's random walk, and the law is the inverse Gamma law of shape 2
+    and scale eta (KS <= 0.01)."""
+    w = rbm_inputs.params_of("wealth1d-n2^20-p2")
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, w["steps"])
+    rbm.rbm_check(ctx)
+    x, _ = state(ctx)
+    y = x[:, 0].astype(np.float64)
+    eta = float(y.mean())
+    ks = ora.ks_distance(y, lambda v: ora.inverse_gamma_cdf(v, 2.0, eta))
+    say("wealth eta", eta, "initial", float(x0.mean()), "KS", ks)
+    assert np.all(y > 0)
+    assert abs(eta - math.sqrt(2 / math.pi)) < 0.03
+    assert ks <= 0.01
