@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT, K_WEALTH_SPLIT = 0, 1, 2, 3, 4
+K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT, K_WEALTH_SPLIT, K_HAMILTON = 0, 1, 2, 3, 4, 5
 
 
 class _Params(ctypes.Structure):
@@ -45,6 +45,8 @@ class Params:
     sys: int = 0
 
     def c(self) -> _Params:
+        if self.kernel == K_HAMILTON and (self.d != 2 or self.sigma != 0.0):
+            raise ValueError("the Hamiltonian system has records (x, u) (d = 2) and no noise (sigma = 0)")
         return _Params(self.d, self.kernel, self.kparam, self.beta, self.sigma,
                        self.dt, self.seed, self.sys)
 

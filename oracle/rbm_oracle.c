@@ -130,7 +130,7 @@ void ora_normals(uint64_t seed, uint32_t sys, uint32_t m, uint32_t id, double z[
 /* ------------------------------------------------------------------------ */
 
 enum { ORA_K_GAUSS = 0, ORA_K_SOFTCOULOMB = 1, ORA_K_ATTREP = 2, ORA_K_COULOMB_SPLIT = 3,
-       ORA_K_WEALTH_SPLIT = 4 };
+       ORA_K_WEALTH_SPLIT = 4, ORA_K_HAMILTON = 5 };
 
 typedef struct {
     int32_t d;          /* space dimension, 1..3 */
@@ -153,9 +153,18 @@ typedef struct {
  *   WEALTH_SPLIT  K(x) = -a x, the trading interaction phi(y) = y^2/2 of the
  *               wealth model of Sec. 5 (a = kappa), stepped by splitting:
  *               exact pair flow, then exact multiplicative noise (below)
+ *   HAMILTON    the second-order system of Sec. 4.1 / Appendix A in one
+ *               space dimension: a record is (x, u) (d = 2, u the Verlet
+ *               velocity), the force x/(x^2 + a) acts between positions
+ *               only (K of a record difference is (K1(x_i - x_j), 0))
  * All are odd: K(-x) = -K(x). */
 void ora_pair_kernel(int32_t kernel, int32_t d, double a, const double *x, double *out)
 {
+    if (kernel == ORA_K_HAMILTON) {
+        out[0] = x[0] / (x[0] * x[0] + a);
+        for (int k = 1; k < d; ++k) out[k] = 0.0;
+        return;
+    }
     double r2 = 0.0;
     for (int k = 0; k < d; ++k) r2 += x[k] * x[k];
     double s;
@@ -361,13 +370,30 @@ static void gbm_update(const ora_params *prm, int64_t n, uint32_t m, double *x)
     }
 }
 
+/* The Verlet scheme of Sec. 4.1 for x'' = F (records (x, u)), in the form
+ *   u_{m+1} = u_m + h (F_m - beta x_m),  x_{m+1} = x_m + dt u_{m+1},
+ * h = dt for m >= 1 and h = dt/2 at m = 0, where u_0 is the initial
+ * velocity: x_1 = x_0 + dt v_0 + dt^2 F_0 / 2 and, with u_m = (x_m -
+ * x_{m-1}) / dt, x_{m+1} = 2 x_m - x_{m-1} + dt^2 F_m. */
+static void verlet_update(const ora_params *prm, int64_t n, uint32_t m, const double *f, double *x)
+{
+    const double h = m == 0 ? 0.5 * prm->dt : prm->dt;
+    for (int64_t i = 0; i < n; ++i) {
+        const double xi = x[i * 2], ui = x[i * 2 + 1];
+        const double u1 = ui + h * (f[i * 2] - prm->beta * xi);
+        x[i * 2 + 1] = u1;
+        x[i * 2] = xi + prm->dt * u1;
+    }
+}
+
 /* One RBM-1 step m (Algorithm 1): draw the division from the slot order,
  * compute batch forces at the old positions, update.  slots is replaced by
  * the new order (the sorted permutation).  COULOMB_SPLIT (p = 2, N even):
  * each pair moves by its exact flow over dt, then the external field and
  * the noise act by one Euler-Maruyama step from the moved positions
  * (Sec. 2.3 splitting, Sec. 4.2).  WEALTH_SPLIT (p = 2, N even): the pair
- * flow of K = -kappa x, then the exact multiplicative noise (Sec. 5). */
+ * flow of K = -kappa x, then the exact multiplicative noise (Sec. 5).
+ * HAMILTON: the batch forces, then the Verlet update. */
 void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
                   double *x, uint32_t *slots)
 {
@@ -401,7 +427,10 @@ void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
     } else {
         ora_rbm_forces(prm, n, p, x, slots, f);
     }
-    euler_update(prm, n, m, f, x);
+    if (prm->kernel == ORA_K_HAMILTON)
+        verlet_update(prm, n, m, f, x);
+    else
+        euler_update(prm, n, m, f, x);
     free(f);
 }
 
@@ -422,7 +451,10 @@ void ora_direct_step(const ora_params *prm, int64_t n, uint32_t m, double *x)
     uint32_t *ids = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
     for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
     ora_direct_forces(prm, n, x, ids, n, f);
-    euler_update(prm, n, m, f, x);
+    if (prm->kernel == ORA_K_HAMILTON)
+        verlet_update(prm, n, m, f, x);
+    else
+        euler_update(prm, n, m, f, x);
     free(ids);
     free(f);
 }

@@ -12,6 +12,9 @@ data of eq. (1.2)):
   dyson1d     d=1, X0 ~ U[-3, 3]             (1-D softened-Coulomb workload)
   attrep3d    d=3, X0 ~ N(0, I)              (3-D attraction-repulsion)
   semicircle  d=1, X0 ~ sqrt(4 - x^2)/(2 pi) (the initial law of Sec. 4.1)
+  absnormal   d=1, X0 ~ |N(0, 1)|            (initial wealth, Sec. 5)
+  hamilton1d  d=2 records (x, v): x semicircle as above, v ~ N(0, 1)
+              (the second-order example of Sec. 4.1)
 """
 from __future__ import annotations
 
@@ -42,6 +45,12 @@ def semicircle(n: int, radius: float = 2.0, seed: int = 1) -> np.ndarray:
     return (r * np.cos(th)).astype(np.float32).reshape(n, 1)
 
 
+def hamilton(n: int, seed: int = 1) -> np.ndarray:
+    """N x 2 float32 records (x, v) of the second-order example of Sec. 4.1:
+    x from the radius-2 semicircle, v ~ N(0, 1), independent."""
+    return np.concatenate([semicircle(n, 2.0, seed), normal(n, 1, seed + 1)], axis=1)
+
+
 def ensemble_sizes(s: int, nmin: int = 64, nmax: int = 65536, seed: int = 1) -> np.ndarray:
     """S system sizes, log-uniform on [nmin, nmax] (int64)."""
     u = _gen(seed).random(s)
@@ -62,6 +71,8 @@ def workload(name: str, n: int, seed: int = 1) -> np.ndarray:
         return semicircle(n, 2.0, seed)
     if name == "absnormal":  # initial wealth |N(0, 1)| (Sec. 5)
         return np.abs(normal(n, 1, seed))
+    if name == "hamilton1d":  # (x, v): semicircle positions, normal velocities (Sec. 4.1)
+        return hamilton(n, seed)
     raise ValueError(f"unknown workload {name!r}")
 
 
@@ -83,6 +94,10 @@ WORKLOADS = {
     # pair flow and exact multiplicative noise, wealth started at |N(0, 1)|
     "wealth1d-n2^20-p2": dict(d=1, kernel=4, n=1 << 20, p=2, kparam=1.0, beta=0.0, sigma=2.0 ** 0.5,
                               dt=1e-3, seed=1, init="absnormal", steps=3000),
+    # second-order (Hamiltonian) system of Sec. 4.1: x'' = F with
+    # K = x/(1 + x^2), Verlet, T = 1; records (x, u)
+    "hamilton1d-n2^20-p2": dict(d=2, kernel=5, n=1 << 20, p=2, kparam=1.0, beta=0.0, sigma=0.0,
+                                dt=2.0 ** -7, seed=1, init="hamilton1d", steps=128),
     # the Gaussian workload at 2^22 particles (control-variate comparison)
     "gauss2d-n2^22-p2": dict(d=2, kernel=0, n=1 << 22, p=2, kparam=0.0, beta=1.0, sigma=0.5,
                              dt=1e-3, seed=1, init="gauss2d", steps=1000),

@@ -561,3 +561,141 @@ def test_wealth_reaches_the_inverse_gamma_equilibrium(ora):
     eta = float(x1.mean())
     assert ora.ks_distance(x1[:, 0], lambda v: ora.inverse_gamma_cdf(v, 2.0, eta)) < 0.03
     assert np.all(x1 > 0)
+
+
+# --------------------------------------------------------------------------
+# the second-order (Hamiltonian) system with Verlet (Sec. 4.1, Appendix A)
+# --------------------------------------------------------------------------
+
+def _hamilton(ora, dt, seed=1, beta=0.0):
+    return ora.Params(d=2, kernel=ora.K_HAMILTON, kparam=1.0, beta=beta, sigma=0.0, dt=dt, seed=seed)
+
+
+def test_hamiltonian_kernel_acts_between_positions(ora):
+    """Records are (x, u): the pair force is (x/(1 + x^2), 0), the Sec. 4.1
+    kernel on the position difference, whatever the velocities."""
+    for dx, du in [(0.5, 3.0), (-2.0, -1.0), (0.0, 7.0)]:
+        k = ora.pair_kernel(ora.K_HAMILTON, 2, 1.0, [dx, du])
+        np.testing.assert_array_equal(k, [dx / (1.0 + dx * dx), 0.0])
+
+
+def test_hamiltonian_rejects_noise_and_other_d(ora):
+    with pytest.raises(ValueError):
+        ora.Params(d=2, kernel=ora.K_HAMILTON, kparam=1.0, beta=0.0, sigma=0.1, dt=0.1).c()
+    with pytest.raises(ValueError):
+        ora.Params(d=1, kernel=ora.K_HAMILTON, kparam=1.0, beta=0.0, sigma=0.0, dt=0.1).c()
+
+
+@pytest.mark.parametrize("p", [2, 3, 0])
+def test_verlet_velocity_form_is_the_two_step_recursion(ora, p):
+    """The stored (x, u) update is the paper's position-only Verlet scheme,
+    X_1 = X_0 + tau V_0 + tau^2 F_0 / 2 and X_{n+1} = 2 X_n - X_{n-1} +
+    tau^2 F_n, with F the mean-field force of the step: the full system's
+    (p = 0 here) or RBM-1's batch force of that step's division."""
+    n, tau = 41, 2.0 ** -5
+    s0 = rbm_inputs.hamilton(n, seed=2).astype(np.float64)
+    prm = _hamilton(ora, tau, seed=3)
+    xs = [s0[:, 0].copy()]
+    s, slots = s0.copy(), np.arange(n)
+    for m in range(6):
+        if p == 0:
+            f = ora.direct_forces(prm, s)
+            s = ora.direct_step(prm, m, s)
+        else:
+            f = ora.rbm_forces(prm, p, s, ora.permutation(prm, m, slots))
+            s, slots = ora.rbm_step(prm, p, m, s, slots)
+        np.testing.assert_array_equal(f[:, 1], 0.0)
+        if m == 0:
+            want = xs[0] + tau * s0[:, 1] + 0.5 * tau * tau * f[:, 0]
+        else:
+            want = 2.0 * xs[-1] - xs[-2] + tau * tau * f[:, 0]
+        np.testing.assert_allclose(s[:, 0], want, rtol=0, atol=1e-13)
+        xs.append(s[:, 0].copy())
+
+
+def test_direct_verlet_converges_to_the_ode_at_second_order(ora):
+    """The full system x'' = (1/(N-1)) sum_j K(x_i - x_j), v(0) = V_0, is
+    integrated by scipy's DOP853 to 1e-12; the Verlet positions at T = 1
+    approach it like tau^2 (a dropped half kick would make it tau^1, a
+    wrong force would not converge)."""
+    from scipy.integrate import solve_ivp
+    n = 6
+    s0 = rbm_inputs.hamilton(n, seed=5).astype(np.float64)
+
+    def rhs(_t, y):
+        x = y[:n]
+        dx = x[:, None] - x[None, :]
+        return np.concatenate([y[n:], (dx / (1.0 + dx * dx)).sum(axis=1) / (n - 1)])
+
+    sol = solve_ivp(rhs, (0.0, 1.0), np.concatenate([s0[:, 0], s0[:, 1]]), method="DOP853",
+                    rtol=1e-12, atol=1e-13)
+    xt = sol.y[:n, -1]
+    errs = []
+    for k in (4, 5, 6, 7):
+        prm = _hamilton(ora, 2.0 ** -k)
+        s = s0.copy()
+        for m in range(2 ** k):
+            s = ora.direct_step(prm, m, s)
+        errs.append(np.abs(s[:, 0] - xt).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(1.9 < o < 2.1 for o in orders), (errs, orders)
+
+
+def test_hamiltonian_rbm_conserves_momentum(ora):
+    """Odd K: the batch forces cancel, so without a field the mean velocity
+    stays at its initial value and the centre of mass moves with it:
+    mean x_m = mean x_0 + m tau mean v_0.  p = N is the full system."""
+    n, tau, steps = 300, 2.0 ** -5, 32
+    s0 = rbm_inputs.hamilton(n, seed=6).astype(np.float64) + np.array([0.4, 0.25])
+    for p in (2, 5):
+        x, _ = ora.rbm_run(_hamilton(ora, tau, seed=p), p, 0, steps, s0)
+        np.testing.assert_allclose(x[:, 1].mean(), s0[:, 1].mean(), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(x[:, 0].mean(), s0[:, 0].mean() + steps * tau * s0[:, 1].mean(),
+                                   rtol=0, atol=1e-13)
+    prm = _hamilton(ora, tau, beta=1.0)
+    x1, _ = ora.rbm_step(prm, n, 0, s0, np.arange(n))
+    np.testing.assert_allclose(x1, ora.direct_step(prm, 0, s0), rtol=1e-13, atol=1e-15)
+
+
+def test_hamiltonian_centre_of_mass_in_a_harmonic_field(ora):
+    """b(x) = -beta x (Appendix A): the batch forces cancel, so the centre of
+    mass is a harmonic oscillator, x(T) = x0 cos(wT) + v0 sin(wT)/w with
+    w = sqrt(beta); Verlet reaches it at T = 1 to O(tau^2)."""
+    n, beta = 200, 2.0
+    s0 = rbm_inputs.hamilton(n, seed=7).astype(np.float64) + np.array([0.5, -0.3])
+    w = math.sqrt(beta)
+    want = s0[:, 0].mean() * math.cos(w) + s0[:, 1].mean() * math.sin(w) / w
+    errs = []
+    for k in (6, 7):
+        x, _ = ora.rbm_run(_hamilton(ora, 2.0 ** -k, seed=2, beta=beta), 3, 0, 2 ** k, s0)
+        errs.append(abs(x[:, 0].mean() - want))
+    assert errs[0] < 1e-3 and 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+@pytest.mark.slow
+def test_hamiltonian_rbm_error_decays_like_sqrt_tau(ora):
+    """Sec. 4.1 second-order example / Theorem A.1: RBM-1 (p = 2) with Verlet
+    against the fully coupled Verlet solution (tau = 2^-11) at T = 1, from
+    semicircle positions and N(0, 1) velocities: the RMS error of the
+    positions, and of positions and velocities together, falls like
+    tau^(1/2) (the slope the text reports; the figure's reference line is
+    read as 0.2 tau^(1/2))."""
+    n = 256
+    s0 = rbm_inputs.hamilton(n, seed=3).astype(np.float64)
+    ref = _hamilton(ora, 2.0 ** -11)
+    sr = s0.copy()
+    for m in range(2 ** 11):
+        sr = ora.direct_step(ref, m, sr)
+    taus = [2.0 ** -k for k in (4, 5, 6, 7, 8)]
+    ex, exu = [], []
+    for tau in taus:
+        e2, e3 = [], []
+        for seed in range(1, 9):
+            x, _ = ora.rbm_run(_hamilton(ora, tau, seed=seed), 2, 0, int(round(1.0 / tau)), s0)
+            e2.append(ora.rms_error(x[:, 0], sr[:, 0]) ** 2)
+            e3.append(ora.rms_error(x, sr) ** 2)
+        ex.append(math.sqrt(np.mean(e2)))
+        exu.append(math.sqrt(np.mean(e3)))
+    for errs in (ex, exu):
+        slope = np.polyfit(np.log(taus), np.log(errs), 1)[0]
+        assert 0.4 < slope < 0.62, (slope, errs)
