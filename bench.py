@@ -314,6 +314,52 @@ def wealth(args) -> dict:
             "mean_wealth": eta, "ks_vs_inverse_gamma": ora.ks_distance(y, lambda v: ora.inverse_gamma_cdf(v, 2.0, eta))}
 
 
+def hamilton(args) -> dict:
+    """Sec. 4.1's second-order example (x'' = F with K = x/(1+x^2), p = 2,
+    Verlet, tau = 2^-7, T = 1) at N = 2^20 from semicircle positions and
+    N(0, 1) velocities: throughput.  At N = 2^14: the RMS position error at
+    T = 1 against the fully coupled Verlet solution (tau = 2^-11) for
+    tau = 2^-4 .. 2^-8 (2 seeds each) and its log-log slope (Theorem A.1
+    bounds it by C(T) sqrt(tau/(p-1)))."""
+    import numpy as np
+    import torch
+    import oracle as ora
+    import paper_1812_10575_amd as rbm
+    import rbm_inputs
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2")
+    prm = rbm.Params(**{k: w[k] for k in FIELDS})
+    ctx = rbm.rbm_init(prm, torch.from_numpy(rbm_inputs.workload(w["init"], w["n"], w["seed"])).cuda())
+    rbm.rbm_run(ctx, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbm.rbm_run(ctx, w["steps"] - 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rbm.rbm_check(ctx)
+    n = 1 << 14
+    ws = dict(w, n=n, dt=2.0 ** -11)
+    x0 = rbm_inputs.workload(w["init"], n, w["seed"])
+    xr = torch.from_numpy(x0).cuda()
+    pr = rbm.Params(**{k: ws[k] for k in FIELDS})
+    for m in range(2 ** 11):
+        xr = rbm.direct_step(pr, xr, m)
+    xr = xr.cpu().numpy()[:, 0].astype(np.float64)
+    taus = [2.0 ** -k for k in (4, 5, 6, 7, 8)]
+    errs = []
+    for tau in taus:
+        e2 = []
+        for seed in (1, 2):
+            c = rbm.rbm_init(rbm.Params(**{k: dict(ws, dt=tau, seed=seed)[k] for k in FIELDS}),
+                             torch.from_numpy(x0).cuda())
+            rbm.rbm_run(c, int(round(1.0 / tau)))
+            e2.append(ora.rms_error(rbm.rbm_positions(c).cpu().numpy()[:, 0], xr) ** 2)
+        errs.append(math.sqrt(float(np.mean(e2))))
+    slope = float(np.polyfit(np.log(taus), np.log(errs), 1)[0])
+    return {"workload": "hamilton1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": w["steps"] * w["dt"],
+            "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
+            "error_n": n, "error_taus": taus, "rms_position_error": errs, "slope": slope}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +471,7 @@ def main() -> int:
     if not args.no_sweep:
         out["dyson_split"] = dyson_split(args)
         out["wealth"] = wealth(args)
+        out["hamilton"] = hamilton(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

@@ -66,13 +66,27 @@ typedef enum {
  *                     difference times e^{-2 a dt}), then X += -dt beta X and
  *                     the exact multiplicative noise of dX = sigma X dB,
  *                     X *= exp(sigma sqrt(dt) z - sigma^2 dt / 2) (sigma =
- *                     sqrt(2D)).  direct_step does not take this kernel.     */
+ *                     sqrt(2D)).  direct_step does not take this kernel.
+ *   RBM_K_HAMILTON    the second-order (Hamiltonian) system of Sec. 4.1 and
+ *                     Appendix A, x'' = -beta x + 1/(N-1) sum_j K(x_i - x_j)
+ *                     with K(x) = x / (x^2 + a) in one dimension (a = 1: the
+ *                     paper's example; a > 0), integrated by Verlet.  d must
+ *                     be 2: a record is (x, u), u the Verlet velocity; at
+ *                     step 0 u is the initial velocity v_0.  Each step
+ *                     (rbm_step and direct_step alike, F the step's force):
+ *                       u += h (F - beta x),  x += dt u,  h = dt/2 at step 0
+ *                     (step0 = 0 in rbm_init), dt after it, which is
+ *                     x_1 = x_0 + dt v_0 + dt^2 F_0 / 2 and x_{m+1} =
+ *                     2 x_m - x_{m-1} + dt^2 F_m.  sigma must be 0; any p.
+ *                     Forces (rbm_forces, direct_*) are (K(x_i - x_j), 0)
+ *                     sums: the velocity component is 0.                  */
 typedef enum {
     RBM_K_GAUSS = 0,
     RBM_K_SOFTCOULOMB = 1,
     RBM_K_ATTREP = 2,
     RBM_K_COULOMB_SPLIT = 3,
-    RBM_K_WEALTH_SPLIT = 4
+    RBM_K_WEALTH_SPLIT = 4,
+    RBM_K_HAMILTON = 5
 } rbm_kernel;
 
 /* Model, method and stream parameters.  V(x) = beta |x|^2 / 2. */
@@ -299,7 +313,8 @@ rbm_status direct_moments(const rbm_params *prm, const float *d_x, const uint32_
                           int64_t nids, float *d_f, float *d_m2, void *stream);
 
 /* One step of the fully coupled system with the update and NOISE stream of
- * RBM-1 step `step`: d_x_out = d_x + dt (-beta d_x + F) + sigma sqrt(dt) z.
+ * RBM-1 step `step`: d_x_out = d_x + dt (-beta d_x + F) + sigma sqrt(dt) z
+ * (RBM_K_HAMILTON: the Verlet update of step `step`).
  * d_x_out must not alias d_x. */
 rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out,
                        int64_t step, void *stream);

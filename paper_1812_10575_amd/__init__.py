@@ -16,7 +16,6 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librbm.so")
 
 RBM_OK, RBM_ERR_INVALID, RBM_ERR_WORKSPACE, RBM_ERR_HIP, RBM_ERR_UNSUPPORTED, RBM_ERR_DEVICE = range(6)
-RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP = 0, 1, 2
 RBM_MAX_N = 1 << 25
 RBM_MAX_P_MULTI = 64
 
@@ -31,7 +30,7 @@ SYMBOLS = (
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
-RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT, RBM_K_WEALTH_SPLIT = 0, 1, 2, 3, 4
+RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT, RBM_K_WEALTH_SPLIT, RBM_K_HAMILTON = range(6)
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
 

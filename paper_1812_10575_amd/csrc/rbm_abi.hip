@@ -66,8 +66,10 @@ rbm_status check_params(const rbm_params *prm)
 {
     if (!prm) return fail(RBM_ERR_INVALID, "params is NULL");
     if (prm->d < 1 || prm->d > 3) return fail(RBM_ERR_INVALID, "d = %d not in 1..3", prm->d);
-    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_WEALTH_SPLIT)
+    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_HAMILTON)
         return fail(RBM_ERR_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == RBM_K_HAMILTON && (prm->d != 2 || prm->sigma != 0.0 || !(prm->kparam > 0.0)))
+        return fail(RBM_ERR_INVALID, "the Hamiltonian system needs d = 2 records (x, u), sigma = 0 and a > 0");
     if (prm->kernel == RBM_K_WEALTH_SPLIT && !(prm->kparam > 0.0))
         return fail(RBM_ERR_INVALID, "the wealth model needs a trading rate kparam > 0");
     if (prm->kernel == RBM_K_COULOMB_SPLIT && prm->kparam != 0.0)
@@ -106,6 +108,7 @@ int kern_of(int kernel)
 {
     if (kernel == RBM_K_COULOMB_SPLIT) return rbm::K_SOFTCOULOMB;
     if (kernel == RBM_K_WEALTH_SPLIT) return rbm::K_LINEAR;
+    if (kernel == RBM_K_HAMILTON) return rbm::K_HAMILTON;
     return kernel;
 }
 
@@ -204,7 +207,10 @@ StepArgs make_args(const rbm_params *prm, const Plan &pl, uint32_t m, bool pendi
     s.ssd = (float)(prm->sigma * std::sqrt(prm->dt));
     s.pm = m - 1u;
     s.pssd = pending ? s.ssd : 0.0f;
-    s.scheme = prm->kernel == RBM_K_COULOMB_SPLIT ? 1u : prm->kernel == RBM_K_WEALTH_SPLIT ? 2u : 0u;
+    s.scheme = prm->kernel == RBM_K_COULOMB_SPLIT ? 1u
+               : prm->kernel == RBM_K_WEALTH_SPLIT ? 2u
+               : prm->kernel == RBM_K_HAMILTON     ? 3u
+                                                    : 0u;
     s.flowc = (float)std::exp(-2.0 * prm->kparam * prm->dt);
     return s;
 }

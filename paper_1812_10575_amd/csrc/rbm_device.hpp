@@ -88,15 +88,26 @@ template <> struct alignas(16) Rec<3> { float x[3]; uint32_t id; };
 //   GAUSS       s = -exp(-r2)
 //   SOFTCOULOMB s = 1 / (r2 + a)
 //   ATTREP      s = 1 / (r2 + a) - 1
+//   LINEAR      s = -a
+//   HAMILTON    s = 1 / (r2 + a) on the first component only: records are
+//               (x, u) of the second-order system, the force acts between
+//               positions (r2 = (xi - xj)^2) and its u-component is zero
 // ---------------------------------------------------------------------------
-enum : int { K_GAUSS = 0, K_SOFTCOULOMB = 1, K_ATTREP = 2, K_LINEAR = 3 };
+enum : int { K_GAUSS = 0, K_SOFTCOULOMB = 1, K_ATTREP = 2, K_LINEAR = 3, K_HAMILTON = 4 };
+
+// Components of a record that the pair kernel reads and acts on.
+template <int D, int KERN>
+constexpr int kdim()
+{
+    return KERN == K_HAMILTON ? 1 : D;
+}
 
 template <int KERN>
 __device__ __forceinline__ float pair_scale(float r2, float a)
 {
     if constexpr (KERN == K_GAUSS) {
         return -__builtin_amdgcn_exp2f(-1.4426950408889634f * r2);  // -e^{-r2}
-    } else if constexpr (KERN == K_SOFTCOULOMB) {
+    } else if constexpr (KERN == K_SOFTCOULOMB || KERN == K_HAMILTON) {
         return __builtin_amdgcn_rcpf(r2 + a);
     } else if constexpr (KERN == K_LINEAR) {
         return -a;  // K(x) = -a x
@@ -110,16 +121,17 @@ template <int D, int KERN>
 __device__ __forceinline__ void add_pair(const float (&xi)[D], const float *xj, float a,
                                          float (&acc)[D])
 {
-    float dx[D];
+    constexpr int DK = kdim<D, KERN>();
+    float dx[DK];
     float r2 = 0.0f;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
+    for (int k = 0; k < DK; ++k) {
         dx[k] = xi[k] - xj[k];
         r2 = fmaf(dx[k], dx[k], r2);
     }
     const float s = pair_scale<KERN>(r2, a);
 #pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] = fmaf(s, dx[k], acc[k]);
+    for (int k = 0; k < DK; ++k) acc[k] = fmaf(s, dx[k], acc[k]);
 }
 
 // Parameters of one step, passed by value to every kernel of the step.
@@ -141,7 +153,8 @@ struct StepArgs {
     float pssd;      // its amplitude (0: none pending)
     uint32_t scheme; // 0: Euler-Maruyama; batches of two move by their exact pair flow,
                      // 1: of K(x) = x/|x|^2 (additive noise), 2: of K(x) = -a x, with
-                     //    multiplicative noise x <- x exp(sigma sqrt(dt) z - sigma^2 dt / 2)
+                     //    multiplicative noise x <- x exp(sigma sqrt(dt) z - sigma^2 dt / 2);
+                     // 3: Verlet for records (x, u) of the second-order system (no noise)
     float flowc;     // scheme 2: e^{-2 a dt}, the decay of a pair's difference over a step
 };
 
@@ -177,6 +190,12 @@ __device__ __forceinline__ void pair_flow(float dt, const float (&xi)[D], const 
     for (int k = 0; k < D; ++k) yi[k] = fmaf(h, u[k], c[k]);
 }
 
+// Pair-flow schemes: a batch of two moves by the exact flow of its pair.
+__device__ __forceinline__ bool pair_flow_scheme(const StepArgs &s)
+{
+    return s.scheme == 1u || s.scheme == 2u;
+}
+
 // Batch [bs, be) of sorted rank r: groups of p, the last also takes the
 // n mod p leftover ranks.
 __device__ __forceinline__ void batch_of(const StepArgs &s, uint32_t r, uint32_t &bs, uint32_t &be)
@@ -192,9 +211,23 @@ __device__ __forceinline__ void batch_of(const StepArgs &s, uint32_t r, uint32_t
 // positions next (deferred noise, below), where the ALU is otherwise idle.
 // The FMAs are written out so that every kernel rounds the update the same
 // way (no contraction left to the compiler).
+//
+// Scheme 3 (the second-order system x'' = b(x) + F, b = -beta x, Sec. 4.1
+// and Appendix A): the record is (x, u), u the Verlet velocity, and
+//   u <- u + h (F - beta x),  x <- x + dt u,   h = dt/2 at step 0, else dt,
+// which is x_1 = x_0 + dt v_0 + dt^2 F_0 / 2 and, with u = (x_m - x_{m-1})/dt,
+// x_{m+1} = 2 x_m - x_{m-1} + dt^2 F_m.
 template <int D>
 __device__ __forceinline__ void drift_update(const StepArgs &s, float (&x)[D], const float (&f)[D])
 {
+    if constexpr (D == 2) {
+        if (s.scheme == 3u) {
+            const float h = s.m == 0u ? 0.5f * s.dt : s.dt;
+            x[1] = fmaf(h, fmaf(-s.beta, x[0], f[0]), x[1]);
+            x[0] = fmaf(s.dt, x[1], x[0]);
+            return;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = fmaf(s.dt, fmaf(-s.beta, x[k], f[k]), x[k]);
 }
@@ -223,6 +256,10 @@ template <int D>
 __device__ __forceinline__ void em_update(const StepArgs &s, float (&x)[D], const float (&f)[D],
                                           uint32_t id)
 {
+    if (s.scheme == 3u) {  // Verlet: no noise
+        drift_update<D>(s, x, f);
+        return;
+    }
     float z[D];
     if (s.ssd != 0.0f) {
         noise<D>(id, s.m, s.sys, s.k0, s.k1, z);

@@ -217,15 +217,16 @@ __device__ void batches(const StepArgs &s, const Team &tm, const Rec<D> *src, ui
             for (int i = 0; i < P; ++i)
 #pragma unroll
                 for (int j = i + 1; j < P; ++j) {
-                    float dx[D], r2 = 0.0f;
+                    constexpr int DK = kdim<D, KERN>();
+                    float dx[DK], r2 = 0.0f;
 #pragma unroll
-                    for (int c = 0; c < D; ++c) {
+                    for (int c = 0; c < DK; ++c) {
                         dx[c] = x[i][c] - x[j][c];
                         r2 = fmaf(dx[c], dx[c], r2);
                     }
                     const float sc = pair_scale<KERN>(r2, s.a);
 #pragma unroll
-                    for (int c = 0; c < D; ++c) {
+                    for (int c = 0; c < DK; ++c) {
                         f[i][c] = fmaf(sc, dx[c], f[i][c]);
                         f[j][c] = fmaf(-sc, dx[c], f[j][c]);
                     }

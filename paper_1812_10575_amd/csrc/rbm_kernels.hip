@@ -438,7 +438,7 @@ __device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, u
         id[i] = r.id;
     }
     if constexpr (P == 2) {
-        if (s.scheme != 0 && !fout) {
+        if (pair_flow_scheme(s) && !fout) {
             // the pair moves by its exact flow, then the external field acts
             float y[2][D], zero[D] = {};
             if (s.scheme == 1) {
@@ -457,15 +457,16 @@ __device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, u
     for (int i = 0; i < P; ++i) {
 #pragma unroll
         for (int j = i + 1; j < P; ++j) {
-            float dx[D], r2 = 0.0f;
+            constexpr int DK = kdim<D, KERN>();
+            float dx[DK], r2 = 0.0f;
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
+            for (int c = 0; c < DK; ++c) {
                 dx[c] = x[i][c] - x[j][c];
                 r2 = fmaf(dx[c], dx[c], r2);
             }
             const float sc = pair_scale<KERN>(r2, s.a);
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
+            for (int c = 0; c < DK; ++c) {
                 f[i][c] = fmaf(sc, dx[c], f[i][c]);
                 f[j][c] = fmaf(-sc, dx[c], f[j][c]);
             }
@@ -706,7 +707,7 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
     const uint32_t tid = threadIdx.x;
     if (tid < sz) sh[tid] = dst[bs + tid];
     __syncthreads();
-    if (tid < sz && s.scheme != 0 && !fout && sz == 2) {
+    if (tid < sz && pair_flow_scheme(s) && !fout && sz == 2) {
         // a pair moves by its exact flow (the same operations as in the sort kernel)
         const Rec<D> me = sh[tid];
         float xi[D], y[D];
@@ -838,6 +839,7 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
                                                 float *__restrict__ out, int step,
                                                 float *__restrict__ m2)
 {
+    constexpr int DK = kdim<D, KERN>();
     __shared__ float tile[TPB * D];
     const uint32_t t = blockIdx.x * TPB + threadIdx.x;
     const bool active = t < nids;
@@ -864,33 +866,33 @@ __global__ __launch_bounds__(TPB) void k_direct(StepArgs s, const float *__restr
         for (int c = 0; c < D; ++c) part[c] = 0.0f;
         if (m2) {
             for (uint32_t jj = 0; jj < cntj; ++jj) {
-                float dx[D];
+                float dx[DK];
                 float r2 = 0.0f;
 #pragma unroll
-                for (int c = 0; c < D; ++c) {
+                for (int c = 0; c < DK; ++c) {
                     dx[c] = xi[c] - tile[jj * D + c];
                     r2 = fmaf(dx[c], dx[c], r2);
                 }
                 float sc = pair_scale<KERN>(r2, s.a);
                 if constexpr (SELF) sc = (base + jj == i) ? 0.0f : sc;
 #pragma unroll
-                for (int c = 0; c < D; ++c) part[c] = fmaf(sc, dx[c], part[c]);
+                for (int c = 0; c < DK; ++c) part[c] = fmaf(sc, dx[c], part[c]);
                 part2 = fmaf(sc * sc, r2, part2);
             }
             acc2 += (double)part2;
         } else
         for (uint32_t jj = 0; jj < cntj; ++jj) {
-            float dx[D];
+            float dx[DK];
             float r2 = 0.0f;
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
+            for (int c = 0; c < DK; ++c) {
                 dx[c] = xi[c] - tile[jj * D + c];
                 r2 = fmaf(dx[c], dx[c], r2);
             }
             float sc = pair_scale<KERN>(r2, s.a);
             if constexpr (SELF) sc = (base + jj == i) ? 0.0f : sc;
 #pragma unroll
-            for (int c = 0; c < D; ++c) part[c] = fmaf(sc, dx[c], part[c]);
+            for (int c = 0; c < DK; ++c) part[c] = fmaf(sc, dx[c], part[c]);
         }
 #pragma unroll
         for (int c = 0; c < D; ++c) acc[c] += (double)part[c];
@@ -1122,6 +1124,9 @@ hipError_t step_d(const Plan &pl, const StepArgs &s, int kernel, void *ws, hipSt
     case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     case K_LINEAR: return step_dk<D, K_LINEAR>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    case K_HAMILTON:
+        if constexpr (D == 2) return step_dk<D, K_HAMILTON>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+        return hipErrorInvalidValue;
     default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
     }
 }
@@ -1148,6 +1153,9 @@ hipError_t direct_d(const StepArgs &s, int kernel, const float *x, const uint32_
     case K_GAUSS: return direct_dk<D, K_GAUSS>(s, x, ids, nids, out, step, m2, st);
     case K_SOFTCOULOMB: return direct_dk<D, K_SOFTCOULOMB>(s, x, ids, nids, out, step, m2, st);
     case K_LINEAR: return direct_dk<D, K_LINEAR>(s, x, ids, nids, out, step, m2, st);
+    case K_HAMILTON:
+        if constexpr (D == 2) return direct_dk<D, K_HAMILTON>(s, x, ids, nids, out, step, m2, st);
+        return hipErrorInvalidValue;
     default: return direct_dk<D, K_ATTREP>(s, x, ids, nids, out, step, m2, st);
     }
 }

@@ -425,3 +425,107 @@ def test_wealth_reaches_the_inverse_gamma_law_at_scale():
     assert np.all(y > 0)
     assert abs(eta - math.sqrt(2 / math.pi)) < 0.03
     assert ks <= 0.01
+
+
+# --------------------------------------------------------------------------
+# the second-order (Hamiltonian) system with Verlet (Sec. 4.1, Appendix A)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,p", [(1024, 2), (20001, 3), (300002, 2), (100003, 7), (65536, 8), (1 << 20, 2)])
+def test_hamilton_matches_the_oracle(n, p):
+    """Records (x, u): permutation bit-exact and e1 <= 1e-5 for the first
+    three steps (the half kick of step 0, then full kicks); the batch forces
+    have a zero velocity component."""
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=n, p=p)
+    say("hamilton", n, p)
+    ctx, _ = start(w)
+    o = op(w)
+    for m in range(3):
+        xm, sm = state(ctx)
+        rbm.rbm_step(ctx)
+        x1, s1 = state(ctx)
+        xo, so = ora.rbm_step(o, p, m, xm.astype(np.float64), sm)
+        assert np.array_equal(s1, so), m
+        assert e_rel(x1, xo) <= 1e-5, (m, e_rel(x1, xo))
+    rbm.rbm_check(ctx)
+    x, s = state(ctx)
+    f = rbm.rbm_forces(ctx, 3).cpu().numpy()
+    assert np.all(f[:, 1] == 0.0)
+    fo = ora.rbm_forces(o, p, x.astype(np.float64), ora.permutation(o, 3, s))
+    assert e_rel(f, fo) <= 1e-5
+
+
+def test_hamilton_hundred_steps_and_direct_verlet():
+    """100 RBM-1 Verlet steps against the oracle (e100 <= 1e-3); the fully
+    coupled Verlet step (direct_step) against the oracle's at steps 0 and 1,
+    and its forces with a zero velocity component."""
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=20000, p=2)
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, 100)
+    x1, s1 = state(ctx)
+    xo, so = ora.rbm_run(op(w), 2, 0, 100, x0.astype(np.float64))
+    assert np.array_equal(s1, so)
+    assert e_rel(x1, xo) <= 1e-3, e_rel(x1, xo)
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=3001)
+    x = x0_of(w)
+    xt = torch.from_numpy(x).cuda()
+    for m in (0, 1):
+        y = rbm.direct_step(gp(w), xt, m).cpu().numpy()
+        assert e_rel(y, ora.direct_step(op(w), m, x.astype(np.float64))) <= 1e-5, m
+    f = rbm.direct_forces(gp(w), xt).cpu().numpy()
+    assert np.all(f[:, 1] == 0.0)
+    assert e_rel(f, ora.direct_forces(op(w), x.astype(np.float64))) <= 1e-5
+
+
+def test_hamilton_rejects_noise_and_other_d():
+    for over in ({"sigma": 0.1}, {"d": 1}, {"d": 3}, {"kparam": 0.0}):
+        w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=1024, **over)
+        with pytest.raises(rbm.RbmError):
+            rbm.rbm_workspace_size(gp(w))
+
+
+def test_hamilton_full_size_momentum_and_centre_of_mass():
+    """N = 2^20, tau = 2^-7, T = 1 (the timed configuration): the batch
+    forces cancel, so the mean velocity stays at its start value and the
+    centre of mass moves with it (FP32 sums of 2^20 terms: 1e-5)."""
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2")
+    ctx, x0 = start(w)
+    rbm.rbm_run(ctx, w["steps"])
+    rbm.rbm_check(ctx)
+    x, _ = state(ctx)
+    x = x.astype(np.float64)
+    v0 = float(x0[:, 1].astype(np.float64).mean())
+    c0 = float(x0[:, 0].astype(np.float64).mean())
+    say("mean u", x[:, 1].mean(), v0, "mean x", x[:, 0].mean(), c0 + v0)
+    assert abs(x[:, 1].mean() - v0) < 1e-5
+    assert abs(x[:, 0].mean() - (c0 + w["steps"] * w["dt"] * v0)) < 1e-5
+    assert np.all(np.isfinite(x))
+
+
+def test_hamilton_error_decays_like_sqrt_tau_on_the_gpu():
+    """Theorem A.1 on the GPU path at N = 2^14: RBM-1 (p = 2) Verlet against
+    the fully coupled Verlet solution (tau = 2^-11, direct_step) at T = 1;
+    the RMS position error over 4 seeds falls like tau^(1/2), and is the
+    size the oracle finds at N = 256 (the bound does not depend on N)."""
+    n = 1 << 14
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=n, dt=2.0 ** -11)
+    x0 = x0_of(w)
+    xr = torch.from_numpy(x0).cuda()
+    for m in range(2 ** 11):
+        xr = rbm.direct_step(gp(w), xr, m)
+    xr = xr.cpu().numpy().astype(np.float64)
+    taus = [2.0 ** -k for k in (4, 5, 6, 7, 8)]
+    errs = []
+    for tau in taus:
+        e2 = []
+        for seed in range(1, 5):
+            ws = dict(w, dt=tau, seed=seed)
+            ctx, _ = start(ws, x0)
+            rbm.rbm_run(ctx, int(round(1.0 / tau)))
+            x, _ = state(ctx)
+            e2.append(ora.rms_error(x[:, 0], xr[:, 0]) ** 2)
+        errs.append(math.sqrt(np.mean(e2)))
+    slope = np.polyfit(np.log(taus), np.log(errs), 1)[0]
+    say("hamilton errors", errs, "slope", slope)
+    assert 0.4 < slope < 0.62, (slope, errs)
+    assert 0.02 < errs[0] < 0.08, errs
