@@ -82,6 +82,9 @@ def _load():
     lib.ora_rbm_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_int64, f64p, u32p]
     lib.ora_direct_step.argtypes = [pp, ctypes.c_int64, ctypes.c_uint32, f64p]
+    lib.ora_rbmr_members.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, u32p]
+    lib.ora_rbmr_apply.argtypes = [pp, ctypes.c_int32, ctypes.c_uint64, u32p, f64p]
+    lib.ora_rbmr_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, f64p]
     _lib = lib
     return lib
 
@@ -210,6 +213,43 @@ def direct_step(prm: Params, m: int, x) -> np.ndarray:
     """One step of the fully coupled system, same update and noise as RBM-1."""
     xv = _f64(x).copy()
     _load().ora_direct_step(ctypes.byref(prm.c()), xv.shape[0], m, _p(xv, ctypes.c_double))
+    return xv
+
+
+# --------------------------------------------------------------------------
+# RBM-r (Sec. 2.2): one random batch per iteration, drawn with replacement
+# --------------------------------------------------------------------------
+
+def _rbmr_check(prm: Params, n: int, p: int):
+    if prm.kernel not in (K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT):
+        raise ValueError("RBM-r takes the Euler kernels and the split Coulomb kernel")
+    if not 2 <= p <= min(n, 64) or (prm.kernel == K_COULOMB_SPLIT and p != 2):
+        raise ValueError("p must be in 2..min(N, 64) (2 for the split Coulomb kernel)")
+
+
+def rbmr_members(prm: Params, n: int, p: int, k: int) -> np.ndarray:
+    """Members m_0 .. m_{p-1} of RBM-r iteration k (uint32, draw order)."""
+    _rbmr_check(prm, n, p)
+    out = np.zeros(p, np.uint32)
+    _load().ora_rbmr_members(ctypes.byref(prm.c()), n, p, k, _p(out, ctypes.c_uint32))
+    return out
+
+
+def rbmr_apply(prm: Params, p: int, k: int, members, x) -> np.ndarray:
+    """Iteration k of RBM-r on the given members (p distinct ids)."""
+    xv = _f64(x).copy()
+    mv = _u32(members).copy()
+    _rbmr_check(prm, xv.shape[0], p)
+    assert mv.size == p and len(set(mv.tolist())) == p and int(mv.max()) < xv.shape[0]
+    _load().ora_rbmr_apply(ctypes.byref(prm.c()), p, k, _p(mv, ctypes.c_uint32), _p(xv, ctypes.c_double))
+    return xv
+
+
+def rbmr_run(prm: Params, p: int, k0: int, niter: int, x) -> np.ndarray:
+    """niter RBM-r iterations k0, k0+1, ... in sequence."""
+    xv = _f64(x).copy()
+    _rbmr_check(prm, xv.shape[0], p)
+    _load().ora_rbmr_run(ctypes.byref(prm.c()), xv.shape[0], p, k0, niter, _p(xv, ctypes.c_double))
     return xv
 
 

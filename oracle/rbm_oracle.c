@@ -458,3 +458,116 @@ void ora_direct_step(const ora_params *prm, int64_t n, uint32_t m, double *x)
     free(ids);
     free(f);
 }
+
+/* ------------------------------------------------------------------------ */
+/* RBM-r: random batches with replacement (Sec. 2.2, Algorithm RBM-r)        */
+/* ------------------------------------------------------------------------ */
+/*
+ * Iteration k (k = 0, 1, ..., below 2^48) picks a set C_k of p distinct
+ * particles at random and moves only them, by the batch SDE over a (pseudo-)
+ * time dt; the next iteration starts from the positions this one left.
+ * N/p iterations stand for one time step dt (RBM-r', the same sequence of
+ * batches read as N/p batches per step).  Random numbers of iteration k:
+ *
+ *   DRAW block b : Philox(c = (k mod 2^32, (k >> 32) | (b << 16), 2, sys))
+ *                  64-bit words U_{2b} = (w1 << 32) | w0, U_{2b+1} = (w3 << 32) | w2
+ *   member r     : v_r = floor(U_r (N - r) / 2^64), and m_r is the v_r-th
+ *                  smallest particle not among m_0 .. m_{r-1} (so C_k is a
+ *                  uniformly random ordered p-subset)
+ *   NOISE slot r : Philox(c = (k mod 2^32, (k >> 32) | (r << 16), 3, sys)),
+ *                  Box-Muller as for RBM-1 -> z_r
+ *
+ * Update of member r (the batch SDE by one Euler-Maruyama step, forces at the
+ * positions the iteration started from):
+ *   x_{m_r} += dt (-beta x_{m_r} + 1/(p-1) sum_{q != r} K(x_{m_r} - x_{m_q}))
+ *              + sigma sqrt(dt) z_r
+ * COULOMB_SPLIT (p = 2): the pair moves by its exact flow over dt, then
+ *   y += dt (-beta y) + sigma sqrt(dt) z_r (the splitting used in Sec. 4.2
+ *   for RBM-r as for RBM-1).
+ */
+static void rbmr_counter(uint64_t k, uint32_t sub, uint32_t stream, uint32_t sys,
+                         uint64_t seed, uint32_t out[4])
+{
+    philox_seeded(seed, (uint32_t)k, (uint32_t)(k >> 32) | (sub << 16), stream, sys, out);
+}
+
+/* Members m_0 .. m_{p-1} of iteration k. */
+void ora_rbmr_members(const ora_params *prm, int64_t n, int32_t p, uint64_t k, uint32_t *mem)
+{
+    uint32_t sorted[64];
+    for (int32_t r = 0; r < p; ++r) {
+        uint32_t w[4];
+        rbmr_counter(k, (uint32_t)(r / 2), 2u, prm->sys, prm->seed, w);
+        const uint64_t u = r % 2 == 0 ? ((uint64_t)w[1] << 32) | w[0] : ((uint64_t)w[3] << 32) | w[2];
+        uint64_t v = (uint64_t)(((unsigned __int128)u * (uint64_t)(n - r)) >> 64);
+        /* the v-th smallest of the particles not drawn yet: step over every
+           drawn particle at or below the running candidate, smallest first */
+        for (int32_t q = 0; q < r; ++q)
+            if (sorted[q] <= v) ++v;
+        mem[r] = (uint32_t)v;
+        int32_t q = r;
+        while (q > 0 && sorted[q - 1] > mem[r]) {
+            sorted[q] = sorted[q - 1];
+            --q;
+        }
+        sorted[q] = mem[r];
+    }
+}
+
+/* Normals of noise slot r of iteration k. */
+static void rbmr_normals(const ora_params *prm, uint64_t k, uint32_t r, double z[4])
+{
+    uint32_t o[4];
+    rbmr_counter(k, r, 3u, prm->sys, prm->seed, o);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int h = 0; h < 2; ++h) {
+        const double u0 = ora_uniform(o[2 * h]);
+        const double u1 = ora_uniform(o[2 * h + 1]);
+        const double rr = sqrt(-2.0 * log(u0));
+        z[2 * h] = rr * cos(two_pi * u1);
+        z[2 * h + 1] = rr * sin(two_pi * u1);
+    }
+}
+
+/* Iteration k on the given members (any p distinct particles). */
+void ora_rbmr_apply(const ora_params *prm, int32_t p, uint64_t k, const uint32_t *mem, double *x)
+{
+    const int d = prm->d;
+    double y[64][3];
+    const double sq = sqrt(prm->dt);
+    if (prm->kernel == ORA_K_COULOMB_SPLIT) {
+        ora_pair_flow(d, prm->dt, x + (int64_t)mem[0] * d, x + (int64_t)mem[1] * d, y[0], y[1]);
+    } else {
+        for (int32_t r = 0; r < p; ++r) {
+            const double *xr = x + (int64_t)mem[r] * d;
+            double f[3] = {0.0, 0.0, 0.0};
+            for (int32_t q = 0; q < p; ++q) {
+                if (q == r) continue;
+                double dx[3], kv[3];
+                for (int c = 0; c < d; ++c) dx[c] = xr[c] - x[(int64_t)mem[q] * d + c];
+                ora_pair_kernel(prm->kernel, d, prm->kparam, dx, kv);
+                for (int c = 0; c < d; ++c) f[c] += kv[c];
+            }
+            for (int c = 0; c < d; ++c) y[r][c] = xr[c] + prm->dt * (-prm->beta * xr[c] + f[c] / (p - 1));
+        }
+    }
+    for (int32_t r = 0; r < p; ++r) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (prm->sigma != 0.0) rbmr_normals(prm, k, (uint32_t)r, z);
+        for (int c = 0; c < d; ++c) {
+            double v = y[r][c];
+            if (prm->kernel == ORA_K_COULOMB_SPLIT) v += prm->dt * (-prm->beta * v);
+            x[(int64_t)mem[r] * d + c] = v + prm->sigma * sq * z[c];
+        }
+    }
+}
+
+/* niter consecutive iterations k0, k0+1, ... */
+void ora_rbmr_run(const ora_params *prm, int64_t n, int32_t p, uint64_t k0, int64_t niter, double *x)
+{
+    uint32_t mem[64];
+    for (int64_t t = 0; t < niter; ++t) {
+        ora_rbmr_members(prm, n, p, k0 + (uint64_t)t, mem);
+        ora_rbmr_apply(prm, p, k0 + (uint64_t)t, mem, x);
+    }
+}
