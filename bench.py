@@ -314,6 +314,38 @@ def wealth(args) -> dict:
             "mean_wealth": eta, "ks_vs_inverse_gamma": ora.ks_distance(y, lambda v: ora.inverse_gamma_cdf(v, 2.0, eta))}
 
 
+def rbmr(args) -> dict:
+    """Sec. 4.2's Dyson Brownian motion by RBM-r (Sec. 2.2): one random pair
+    per iteration, N/2 iterations per dt = 1e-3, exact pair flow, N = 2^20
+    from the radius-2 semicircle to t = 5: throughput in particle updates
+    per second (p per iteration; N/p iterations make one particle-step each)
+    and the KS distance to the analytic density at the end."""
+    import numpy as np
+    import torch
+    import oracle as ora
+    import paper_1812_10575_amd as rbm
+    import rbm_inputs
+    w = rbm_inputs.params_of("dysonrbmr1d-n2^20-p2")
+    prm = rbm.Params(**{k: w[k] for k in FIELDS})
+    x = torch.from_numpy(rbm_inputs.workload(w["init"], w["n"], w["seed"])).cuda()
+    ws = torch.empty(rbm.rbmr_workspace_size(prm), dtype=torch.uint8, device="cuda")
+    per = w["n"] // w["p"]
+    rbm.rbmr_run(prm, x, 0, 10 * per, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbm.rbmr_run(prm, x, 10 * per, (w["steps"] - 10) * per, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    y = x.cpu().numpy()[:, 0].astype(np.float64)
+    t_end = w["steps"] * w["dt"]
+    sig = 1 + math.exp(-2 * t_end)
+    return {"workload": "dysonrbmr1d-n2^20-p2", "n": w["n"], "iterations": w["steps"] * per, "t": t_end,
+            "value": (w["steps"] - 10) * per * w["p"] / dt, "unit": "particle-steps/s",
+            "us_per_window": 1e6 * dt / (w["steps"] - 10),
+            "ks_vs_analytic": ora.ks_distance(y, lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig))),
+            "m2": float(np.mean(y * y)), "m2_analytic": sig / 2}
+
+
 def hamilton(args) -> dict:
     """Sec. 4.1's second-order example (x'' = F with K = x/(1+x^2), p = 2,
     Verlet, tau = 2^-7, T = 1) at N = 2^20 from semicircle positions and
@@ -472,6 +504,7 @@ def main() -> int:
         out["dyson_split"] = dyson_split(args)
         out["wealth"] = wealth(args)
         out["hamilton"] = hamilton(args)
+        out["rbmr"] = rbmr(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, x0)
     print(json.dumps(out), flush=True)

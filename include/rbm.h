@@ -323,6 +323,51 @@ rbm_status direct_step(const rbm_params *prm, const float *d_x, float *d_x_out,
 const char *rbm_status_str(rbm_status st);
 const char *rbm_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * RBM-r: random batches with replacement (Sec. 2.2, Algorithms RBM-r' and
+ * RBM-r).  Iteration k (0 <= k < 2^48) draws a batch C_k of p distinct
+ * particles, uniformly at random and independently of the other iterations,
+ * and moves only them by the batch SDE over dt, from the positions the
+ * earlier iterations left:
+ *   x_i += dt (-beta x_i + 1/(p-1) sum_{j in C_k, j != i} K(x_i - x_j))
+ *          + sigma sqrt(dt) z
+ * (RBM_K_COULOMB_SPLIT, p = 2: the pair's exact flow over dt, then the field
+ * step and the noise, as in the splitting of Sec. 4.2).  N/p iterations
+ * stand for one time step dt (RBM-r' reads them as the N/p batches of a
+ * step).  Random numbers of iteration k, Philox4x32-10 with the key of
+ * rbm_params.seed, counter (k mod 2^32, (k >> 32) | (s << 16), stream, sys):
+ *   stream 2, s = b: words (w0..w3) -> U_{2b} = w1:w0, U_{2b+1} = w3:w2;
+ *     member r: v = floor(U_r (N - r) / 2^64) and m_r = the v-th smallest
+ *     particle not drawn yet (a uniformly random ordered p-subset)
+ *   stream 3, s = r: the normals of member r (Box-Muller as for RBM-1)
+ * The result is that of running the iterations one after another: the
+ * library runs a window of iterations in rounds of disjoint batches, each
+ * iteration in the first round in which it is the earliest pending one of
+ * all its members, so window and rounds change the speed, never the result.
+ *
+ * rbm_params: d 1..3, kernel RBM_K_GAUSS .. RBM_K_COULOMB_SPLIT (the latter
+ * with p = 2 and kparam = 0), 2 <= p <= min(N, RBM_RBMR_MAX_P), cv = 0.
+ * window: iterations per round schedule, 0 for N/p (at most
+ * RBM_RBMR_MAX_WINDOW).  rounds: parallel rounds per window before the rest
+ * runs in order on one workgroup, 0 for (10 + 3p) ceil(window p / N). */
+#define RBM_RBMR_MAX_P 8
+#define RBM_RBMR_MAX_WINDOW (1u << 22)
+#define RBM_RBMR_MAX_ROUNDS 255
+
+/* Bytes of device workspace rbmr_run needs: 16 N + (p + 2) window +
+ * 4 (rounds + 1), each part rounded up to 256. */
+rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes);
+
+/* Iterations k0 .. k0 + niter - 1 on d_x ([N][d] FP32 positions by particle
+ * id, updated in place), enqueued on stream.  d_ws: caller-owned workspace of
+ * ws_bytes >= rbmr_workspace_size, 256-byte aligned, no contents carried
+ * between calls (so a run split over several calls, k0 continuing, equals
+ * one call).  Errors: RBM_ERR_INVALID / RBM_ERR_UNSUPPORTED for parameters
+ * outside the limits above, RBM_ERR_WORKSPACE, RBM_ERR_HIP for a failed
+ * launch; nothing is enqueued on an argument error. */
+rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window,
+                    int32_t rounds, void *d_ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,10 +26,13 @@ SYMBOLS = (
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
     "cv_init", "cv_set_weights", "cv_get_weights", "cv_features", "cv_grads", "cv_train",
     "rbm_force_sqerr", "ensemble_workspace_size", "ensemble_run", "direct_moments",
+    "rbmr_workspace_size", "rbmr_run",
 )
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
+RBMR_MAX_P = 8
+RBMR_MAX_WINDOW = 1 << 22
 RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT, RBM_K_WEALTH_SPLIT, RBM_K_HAMILTON = range(6)
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
@@ -97,6 +100,8 @@ def lib():
         "ensemble_workspace_size": [ctypes.POINTER(rbm_ensemble), vp, ctypes.POINTER(sz)],
         "ensemble_run": [ctypes.POINTER(rbm_ensemble), vp, vp, vp, i64, i64,
                          ctypes.POINTER(rbm_ensemble_tile), vp, sz, ctypes.c_int32, vp],
+        "rbmr_workspace_size": [pp, i64, ctypes.c_int32, ctypes.POINTER(sz)],
+        "rbmr_run": [pp, vp, i64, i64, i64, ctypes.c_int32, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -284,6 +289,28 @@ def direct_step(prm: Params, x, step: int, out=None, stream=None):
     _expect(out, torch.float32, (prm.n, prm.d), "out")
     _check(lib().direct_step(ctypes.byref(prm.c()), _ptr(x), _ptr(out), step, _stream(stream)))
     return out
+
+
+# ---- RBM-r ------------------------------------------------------------------
+
+def rbmr_workspace_size(prm: Params, window: int = 0, rounds: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().rbmr_workspace_size(ctypes.byref(prm.c()), window, rounds, ctypes.byref(out)))
+    return out.value
+
+
+def rbmr_run(prm: Params, x, k0: int, niter: int, window: int = 0, rounds: int = 0, ws=None, stream=None):
+    """RBM-r iterations k0 .. k0 + niter - 1 in place on x ([N][d] FP32 by
+    particle id); returns x.  ws: a uint8 device tensor of at least
+    rbmr_workspace_size bytes (allocated here if None)."""
+    import torch
+    _expect(x, torch.float32, (prm.n, prm.d), "x")
+    need = rbmr_workspace_size(prm, window, rounds)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check(lib().rbmr_run(ctypes.byref(prm.c()), _ptr(x), k0, niter, window, rounds, _ptr(ws), ws.numel(),
+                          _stream(stream)))
+    return x
 
 
 # ---- control variate -------------------------------------------------------

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbm.so")
-SOURCES = ["rbm_kernels.hip", "rbm_cv.hip", "rbm_ensemble.hip", "rbm_abi.hip"]
+SOURCES = ["rbm_kernels.hip", "rbm_cv.hip", "rbm_ensemble.hip", "rbm_rbmr.hip", "rbm_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -17,6 +17,7 @@
 #include "rbm_cv.hpp"
 #include "rbm_ensemble.hpp"
 #include "rbm_plan.hpp"
+#include "rbm_rbmr.hpp"
 
 using rbm::Plan;
 using rbm::StepArgs;
@@ -846,6 +847,80 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
     if (he != hipSuccess) return hip_fail(he, "ensemble completion");
     if (flags != 0) return fail(RBM_ERR_DEVICE, "a bucket of a streamed system exceeded the LDS capacity");
     return RBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// RBM-r
+// ---------------------------------------------------------------------------
+static_assert(RBMR_MAX_P == RBM_RBMR_MAX_P && RBMR_MAX_WINDOW == RBM_RBMR_MAX_WINDOW,
+              "RBM-r limits of the header and the kernels differ");
+
+static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t rounds, rbm::RbmrLayout *lay)
+{
+    if (!prm) return fail(RBM_ERR_INVALID, "params is NULL");
+    if (prm->d < 1 || prm->d > 3) return fail(RBM_ERR_INVALID, "d = %d not in 1..3", prm->d);
+    if (prm->kernel < RBM_K_GAUSS || prm->kernel > RBM_K_COULOMB_SPLIT)
+        return fail(RBM_ERR_UNSUPPORTED, "RBM-r takes kernels 0..3 (got %d)", prm->kernel);
+    if (prm->n < 2 || prm->n > RBM_MAX_N) return fail(RBM_ERR_INVALID, "N = %lld not in 2..2^25", (long long)prm->n);
+    if (prm->p < 2 || prm->p > RBMR_MAX_P || (int64_t)prm->p > prm->n)
+        return fail(RBM_ERR_UNSUPPORTED, "RBM-r needs 2 <= p <= min(N, %d)", RBMR_MAX_P);
+    if (prm->kernel == RBM_K_COULOMB_SPLIT && (prm->p != 2 || prm->kparam != 0.0))
+        return fail(RBM_ERR_UNSUPPORTED, "the split Coulomb kernel needs p = 2 and kparam = 0");
+    if (prm->cv != 0 || prm->reserved != 0) return fail(RBM_ERR_INVALID, "cv and reserved must be 0");
+    if (!(prm->dt > 0.0) || !std::isfinite(prm->dt)) return fail(RBM_ERR_INVALID, "dt must be > 0");
+    if (!(prm->sigma >= 0.0) || !std::isfinite(prm->sigma)) return fail(RBM_ERR_INVALID, "sigma must be >= 0");
+    if (!(prm->kparam >= 0.0) || !std::isfinite(prm->kparam)) return fail(RBM_ERR_INVALID, "kparam must be >= 0");
+    if (!std::isfinite(prm->beta)) return fail(RBM_ERR_INVALID, "beta must be finite");
+    const int64_t wdef = std::min<int64_t>(std::max<int64_t>(prm->n / prm->p, 1), RBMR_MAX_WINDOW);
+    if (window == 0) window = wdef;
+    if (window < 1 || window > RBMR_MAX_WINDOW)
+        return fail(RBM_ERR_INVALID, "window %lld not in 1..%u", (long long)window, RBMR_MAX_WINDOW);
+    if (rounds == 0) {
+        // about twice the usual depth of a window (touches per particle c = window p / N)
+        const int64_t c = (window * prm->p + prm->n - 1) / prm->n;
+        rounds = (int32_t)std::min<int64_t>((10 + 3 * prm->p) * c, RBM_RBMR_MAX_ROUNDS);
+    }
+    if (rounds < 1 || rounds > RBM_RBMR_MAX_ROUNDS)
+        return fail(RBM_ERR_INVALID, "rounds %d not in 1..%d", rounds, RBM_RBMR_MAX_ROUNDS);
+    *lay = rbm::rbmr_layout((uint32_t)prm->n, (uint32_t)prm->p, (uint32_t)window, (uint32_t)rounds);
+    return RBM_OK;
+}
+
+rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes)
+{
+    if (!bytes) return fail(RBM_ERR_INVALID, "bytes is NULL");
+    rbm::RbmrLayout lay;
+    const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
+    if (st != RBM_OK) return st;
+    *bytes = lay.bytes;
+    return RBM_OK;
+}
+
+rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window, int32_t rounds,
+                    void *d_ws, size_t ws_bytes, void *stream)
+{
+    rbm::RbmrLayout lay;
+    const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
+    if (st != RBM_OK) return st;
+    if (!d_x || !d_ws) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (k0 < 0 || niter < 0 || k0 > (int64_t)1 << 48 || niter > ((int64_t)1 << 48) - k0)
+        return fail(RBM_ERR_INVALID, "iterations k0 .. k0 + niter must lie in 0 .. 2^48");
+    if (ws_bytes < lay.bytes) return fail(RBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, lay.bytes);
+    if (((uintptr_t)d_ws & 255u) != 0) return fail(RBM_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    rbm::RbmrArgs a{};
+    a.n = (uint32_t)prm->n;
+    a.p = (uint32_t)prm->p;
+    a.k0 = (uint32_t)(prm->seed & 0xffffffffu);
+    a.k1 = (uint32_t)(prm->seed >> 32);
+    a.sys = prm->sys;
+    a.inv_p1 = (float)(1.0 / (double)(prm->p - 1));
+    a.a = (float)prm->kparam;
+    a.beta = (float)prm->beta;
+    a.dt = (float)prm->dt;
+    a.ssd = (float)(prm->sigma * std::sqrt(prm->dt));
+    const hipError_t e = rbm::rbmr_launch(a, prm->d, prm->kernel, lay, d_ws, d_x, (uint64_t)k0, (uint64_t)niter,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? RBM_OK : hip_fail(e, "rbmr_run launch");
 }
 
 }  // extern "C"

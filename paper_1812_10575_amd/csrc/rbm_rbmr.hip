@@ -1,0 +1,345 @@
+// RBM-r (Sec. 2.2, Algorithm RBM-r) on the GPU.
+//
+// The method is sequential: iteration k moves the p particles of its batch
+// C_k, starting from the positions the earlier iterations left.  Iterations
+// whose batches are disjoint commute, so a window of W consecutive
+// iterations runs in rounds: an iteration runs in the first round in which
+// it is the earliest pending iteration of every one of its members.  Each
+// iteration then starts from exactly the positions the sequential order
+// gives it, so the result depends neither on the window nor on the rounds
+// (bit for bit: an iteration's arithmetic is the same wherever it runs).
+//
+// One window:
+//   k_rbmr_draw   draws every batch and marks each member with the round-0
+//                 tag of the iteration (64-bit atomic min)
+//   k_rbmr_round  round L: an iteration whose tag is still on all its
+//                 members runs; the others mark their members with the next
+//                 round's tag in the other tag array and queue themselves
+//   k_rbmr_tail   one workgroup runs whatever is pending after the last
+//                 round, in iteration order (usually nothing: the depth of
+//                 a window of N/p random pairs is about 12)
+// Tag of iteration e (its offset in the window) in round g (counting up
+// over the call): (~g << 32) | e.  A later round's tags are below every
+// stale one, so the arrays need no reset between rounds, and within a round
+// the earliest iteration wins.  Round L reads tag array L mod 2 and writes
+// the other, so what it reads was settled before it started.
+#include <hip/hip_runtime.h>
+
+#include "rbm_rbmr.hpp"
+
+namespace rbm {
+namespace {
+
+constexpr int TPB = 256;
+enum : uint32_t { STREAM_RBMR_DRAW = 2u, STREAM_RBMR_NOISE = 3u };
+
+__device__ __forceinline__ uint64_t tag_of(uint32_t g, uint32_t e)
+{
+    return ((uint64_t)(~g) << 32) | e;
+}
+
+__device__ __forceinline__ uint4 rbmr_block(const RbmrArgs &a, uint64_t k, uint32_t sub, uint32_t stream)
+{
+    return philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(k >> 32) | (sub << 16), stream, a.sys), a.k0, a.k1);
+}
+
+// Members of iteration k in draw order: member r takes the 64-bit word
+// U_r, v = floor(U_r (N - r) / 2^64), and becomes the v-th smallest
+// particle not drawn yet (a uniformly random ordered p-subset).
+__device__ __forceinline__ void draw_members(const RbmrArgs &a, uint64_t k, uint32_t (&m)[RBMR_MAX_P])
+{
+    uint32_t srt[RBMR_MAX_P];
+    uint4 w = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int r = 0; r < RBMR_MAX_P; ++r) {
+        if (r < (int)a.p) {
+            if ((r & 1) == 0) w = rbmr_block(a, k, (uint32_t)(r >> 1), STREAM_RBMR_DRAW);
+            const uint64_t u = (r & 1) == 0 ? ((uint64_t)w.y << 32) | w.x : ((uint64_t)w.w << 32) | w.z;
+            uint32_t v = (uint32_t)__umul64hi(u, (uint64_t)(a.n - (uint32_t)r));
+#pragma unroll
+            for (int q = 0; q < RBMR_MAX_P - 1; ++q)
+                if (q < r && srt[q] <= v) ++v;
+            m[r] = v;
+            uint32_t cur = v;  // insert into the sorted list
+#pragma unroll
+            for (int q = 0; q < RBMR_MAX_P; ++q) {
+                if (q < r) {
+                    if (srt[q] > cur) {
+                        const uint32_t t = srt[q];
+                        srt[q] = cur;
+                        cur = t;
+                    }
+                } else if (q == r) {
+                    srt[q] = cur;
+                }
+            }
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void rbmr_noise(const RbmrArgs &a, uint64_t k, uint32_t r, float (&z)[D])
+{
+    const uint4 w = rbmr_block(a, k, r, STREAM_RBMR_NOISE);
+    float b0, b1;
+    box_muller(u24(w.x), u24(w.y), b0, b1);
+    z[0] = b0;
+    if constexpr (D >= 2) z[1] = b1;
+    if constexpr (D >= 3) {
+        float c, e;
+        box_muller(u24(w.z), u24(w.w), c, e);
+        z[2] = c;
+    }
+}
+
+// Iteration k on its members: forces at the positions it starts from, one
+// Euler-Maruyama step of the batch SDE (SPLIT: the exact pair flow of
+// K = x/|x|^2, then the field step), then the noise of its slots.
+template <int D, int KERN, bool SPLIT>
+__device__ __forceinline__ void run_iteration(const RbmrArgs &a, uint64_t k, const uint32_t (&m)[RBMR_MAX_P],
+                                              float *__restrict__ x)
+{
+    float xs[RBMR_MAX_P][D], y[RBMR_MAX_P][D];
+#pragma unroll
+    for (int r = 0; r < RBMR_MAX_P; ++r)
+        if (r < (int)a.p) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) xs[r][c] = x[(size_t)m[r] * D + c];
+        }
+    if constexpr (SPLIT) {
+        pair_flow<D>(a.dt, xs[0], xs[1], y[0]);
+        pair_flow<D>(a.dt, xs[1], xs[0], y[1]);
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) y[r][c] = fmaf(a.dt, -a.beta * y[r][c], y[r][c]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RBMR_MAX_P; ++r) {
+            if (r < (int)a.p) {
+                float f[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) f[c] = 0.0f;
+#pragma unroll
+                for (int q = 0; q < RBMR_MAX_P; ++q)
+                    if (q < (int)a.p && q != r) add_pair<D, KERN>(xs[r], xs[q], a.a, f);
+#pragma unroll
+                for (int c = 0; c < D; ++c) y[r][c] = fmaf(a.dt, fmaf(-a.beta, xs[r][c], f[c] * a.inv_p1), xs[r][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RBMR_MAX_P; ++r)
+        if (r < (int)a.p) {
+            if (a.ssd != 0.0f) {
+                float z[D];
+                rbmr_noise<D>(a, k, (uint32_t)r, z);
+#pragma unroll
+                for (int c = 0; c < D; ++c) y[r][c] = fmaf(a.ssd, z[c], y[r][c]);
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c) x[(size_t)m[r] * D + c] = y[r][c];
+        }
+}
+
+__device__ __forceinline__ void load_members(const RbmrArgs &a, const uint32_t *__restrict__ mem, uint32_t e,
+                                             uint32_t (&m)[RBMR_MAX_P])
+{
+#pragma unroll
+    for (int r = 0; r < RBMR_MAX_P; ++r) m[r] = r < (int)a.p ? mem[(size_t)e * a.p + r] : 0u;
+}
+
+__global__ __launch_bounds__(TPB) void k_rbmr_fill(uint64_t *__restrict__ t, uint32_t n2)
+{
+    const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+    if (i < n2) t[i] = ~(uint64_t)0;
+}
+
+__global__ __launch_bounds__(TPB) void k_rbmr_draw(RbmrArgs a, uint64_t kbase, uint32_t wcur, uint32_t g,
+                                                   uint32_t *__restrict__ mem, uint64_t *first,
+                                                   uint32_t *__restrict__ counts, uint32_t rounds)
+{
+    const uint32_t e = blockIdx.x * TPB + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x <= rounds) counts[threadIdx.x] = 0u;
+    if (e >= wcur) return;
+    uint32_t m[RBMR_MAX_P];
+    draw_members(a, kbase + e, m);
+    const uint64_t t = tag_of(g, e);
+#pragma unroll
+    for (int r = 0; r < RBMR_MAX_P; ++r)
+        if (r < (int)a.p) {
+            mem[(size_t)e * a.p + r] = m[r];
+            atomicMin((unsigned long long *)&first[m[r]], (unsigned long long)t);
+        }
+}
+
+// Round L (tag g): L = 0 takes the whole window, later rounds the queue
+// lin[0 .. counts[L]).  Not-ready iterations go to lout / counts[L + 1].
+template <int D, int KERN, bool SPLIT>
+__global__ __launch_bounds__(TPB) void k_rbmr_round(RbmrArgs a, uint32_t L, uint32_t g, uint64_t kbase, uint32_t wcur,
+                                                    const uint32_t *__restrict__ mem, const uint64_t *__restrict__ tin,
+                                                    uint64_t *tout, const uint32_t *__restrict__ lin,
+                                                    uint32_t *__restrict__ lout, uint32_t *counts, float *__restrict__ x)
+{
+    const uint32_t nin = L == 0 ? wcur : counts[L];
+    const uint64_t t = (uint64_t)(~g) << 32, t1 = (uint64_t)(~(g + 1u)) << 32;
+    for (uint32_t base = blockIdx.x * TPB; base < nin; base += gridDim.x * TPB) {
+        const uint32_t idx = base + threadIdx.x;
+        bool pend = false;
+        uint32_t e = 0;
+        if (idx < nin) {
+            e = L == 0 ? idx : lin[idx];
+            uint32_t m[RBMR_MAX_P];
+            load_members(a, mem, e, m);
+            bool ready = true;
+#pragma unroll
+            for (int r = 0; r < RBMR_MAX_P; ++r)
+                if (r < (int)a.p) ready = ready && tin[m[r]] == (t | e);
+            if (ready) {
+                run_iteration<D, KERN, SPLIT>(a, kbase + e, m, x);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RBMR_MAX_P; ++r)
+                    if (r < (int)a.p) atomicMin((unsigned long long *)&tout[m[r]], (unsigned long long)(t1 | e));
+                pend = true;
+            }
+        }
+        // queue the pending iterations: one atomic per wavefront
+        const uint64_t mask = __ballot(pend);
+        if (mask) {
+            const uint32_t lane = __lane_id();
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            uint32_t q0 = 0;
+            if ((int)lane == leader) q0 = atomicAdd(&counts[L + 1], (uint32_t)__popcll(mask));
+            q0 = __shfl(q0, leader);
+            if (pend) lout[q0 + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = e;
+        }
+    }
+}
+
+// The iterations still pending after the last round, in iteration order, by
+// one thread (the workgroup finds the next one).
+template <int D, int KERN, bool SPLIT>
+__global__ __launch_bounds__(TPB) void k_rbmr_tail(RbmrArgs a, uint32_t rounds, uint64_t kbase,
+                                                   const uint32_t *__restrict__ mem, const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ counts, float *__restrict__ x)
+{
+    const uint32_t n = counts[rounds];
+    if (n == 0) return;
+    __shared__ uint32_t red[TPB];
+    uint32_t last = 0;
+    bool first_pass = true;
+    for (uint32_t it = 0; it < n; ++it) {
+        uint32_t best = 0xffffffffu;
+        for (uint32_t i = threadIdx.x; i < n; i += TPB) {
+            const uint32_t e = list[i];
+            if ((first_pass || e > last) && e < best) best = e;
+        }
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int s = TPB / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        const uint32_t e = red[0];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t m[RBMR_MAX_P];
+            load_members(a, mem, e, m);
+            run_iteration<D, KERN, SPLIT>(a, kbase + e, m, x);
+        }
+        last = e;
+        first_pass = false;
+    }
+}
+
+template <int D, int KERN, bool SPLIT>
+hipError_t launch_dk(const RbmrArgs &a, const RbmrLayout &lay, void *ws, float *x, uint64_t kbase,
+                     uint64_t niter, hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    auto *tags = reinterpret_cast<uint64_t *>(w + lay.off_first);
+    uint64_t *tarr[2] = {tags, tags + a.n};
+    auto *mem = reinterpret_cast<uint32_t *>(w + lay.off_mem);
+    uint32_t *lists[2] = {reinterpret_cast<uint32_t *>(w + lay.off_list0),
+                          reinterpret_cast<uint32_t *>(w + lay.off_list1)};
+    auto *counts = reinterpret_cast<uint32_t *>(w + lay.off_counts);
+    const uint32_t R = lay.rounds;
+    const uint32_t n2 = 2u * a.n;
+    uint32_t g = 0;
+    bool filled = false;
+    for (uint64_t done = 0; done < niter;) {
+        const uint32_t wcur = (uint32_t)((niter - done) < lay.window ? (niter - done) : lay.window);
+        if (!filled || (uint64_t)g + R + 2u >= 0xffffffffull) {
+            hipLaunchKernelGGL(k_rbmr_fill, dim3((n2 + TPB - 1) / TPB), dim3(TPB), 0, st, tags, n2);
+            g = 0;
+            filled = true;
+        }
+        const uint32_t g0 = (wcur + TPB - 1) / TPB;
+        hipLaunchKernelGGL(k_rbmr_draw, dim3(g0), dim3(TPB), 0, st, a, kbase + done, wcur, g, mem, tarr[0], counts, R);
+        for (uint32_t L = 0; L < R; ++L) {
+            uint32_t grid = L == 0 ? g0 : g0 >> L;
+            if (grid < 64u) grid = g0 < 64u ? g0 : 64u;
+            hipLaunchKernelGGL((k_rbmr_round<D, KERN, SPLIT>), dim3(grid), dim3(TPB), 0, st, a, L, g + L, kbase + done,
+                               wcur, mem, tarr[L & 1u], tarr[(L + 1u) & 1u], lists[L & 1u], lists[(L + 1u) & 1u],
+                               counts, x);
+        }
+        hipLaunchKernelGGL((k_rbmr_tail<D, KERN, SPLIT>), dim3(1), dim3(TPB), 0, st, a, R, kbase + done, mem,
+                           lists[R & 1u], counts, x);
+        g += R + 1u;
+        done += wcur;
+    }
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_d(const RbmrArgs &a, int kernel, const RbmrLayout &lay, void *ws, float *x, uint64_t kbase,
+                    uint64_t niter, hipStream_t st)
+{
+    switch (kernel) {
+    case K_GAUSS: return launch_dk<D, K_GAUSS, false>(a, lay, ws, x, kbase, niter, st);
+    case K_SOFTCOULOMB: return launch_dk<D, K_SOFTCOULOMB, false>(a, lay, ws, x, kbase, niter, st);
+    case K_ATTREP: return launch_dk<D, K_ATTREP, false>(a, lay, ws, x, kbase, niter, st);
+    default: return launch_dk<D, K_SOFTCOULOMB, true>(a, lay, ws, x, kbase, niter, st);
+    }
+}
+
+size_t al256(size_t v)
+{
+    return (v + 255) & ~(size_t)255;
+}
+
+}  // namespace
+
+RbmrLayout rbmr_layout(uint32_t n, uint32_t p, uint32_t window, uint32_t rounds)
+{
+    RbmrLayout l{};
+    l.window = window;
+    l.rounds = rounds;
+    size_t o = 0;
+    l.off_first = o;
+    o = al256(o + (size_t)2 * n * sizeof(uint64_t));
+    l.off_mem = o;
+    o = al256(o + (size_t)window * p * sizeof(uint32_t));
+    l.off_list0 = o;
+    o = al256(o + (size_t)window * sizeof(uint32_t));
+    l.off_list1 = o;
+    o = al256(o + (size_t)window * sizeof(uint32_t));
+    l.off_counts = o;
+    o = al256(o + (size_t)(rounds + 1) * sizeof(uint32_t));
+    l.bytes = o;
+    return l;
+}
+
+hipError_t rbmr_launch(const RbmrArgs &a, int d, int kernel, const RbmrLayout &lay, void *ws, float *x,
+                       uint64_t kbase, uint64_t niter, hipStream_t st)
+{
+    if (niter == 0) return hipSuccess;
+    switch (d) {
+    case 1: return launch_d<1>(a, kernel, lay, ws, x, kbase, niter, st);
+    case 2: return launch_d<2>(a, kernel, lay, ws, x, kbase, niter, st);
+    default: return launch_d<3>(a, kernel, lay, ws, x, kbase, niter, st);
+    }
+}
+
+}  // namespace rbm

@@ -90,6 +90,10 @@ WORKLOADS = {
     # splitting with the exact pair flow, from the radius-2 semicircle
     "dysonsplit1d-n2^20-p2": dict(d=1, kernel=3, n=1 << 20, p=2, kparam=0.0, beta=1.0,
                                   sigma=1.0 / 1024.0, dt=1e-3, seed=1, init="semicircle2", steps=5000),
+    # the same Dyson Brownian motion by RBM-r: one random pair per iteration,
+    # N/2 iterations per unit dt ("steps" counts such windows)
+    "dysonrbmr1d-n2^20-p2": dict(d=1, kernel=3, n=1 << 20, p=2, kparam=0.0, beta=1.0,
+                                 sigma=1.0 / 1024.0, dt=1e-3, seed=1, init="semicircle2", steps=5000),
     # wealth model of Sec. 5: kappa = D = 1 (sigma = sqrt 2), quadratic trading,
     # pair flow and exact multiplicative noise, wealth started at |N(0, 1)|
     "wealth1d-n2^20-p2": dict(d=1, kernel=4, n=1 << 20, p=2, kparam=1.0, beta=0.0, sigma=2.0 ** 0.5,
