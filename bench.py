@@ -410,6 +410,8 @@ def main() -> int:
     ap.add_argument("--retune", action="store_true", help="ignore the ensemble autotune cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a reference for HBM byte counters)")
+    ap.add_argument("--only", choices=("dyson_split", "wealth", "hamilton", "rbmr", "ensemble"), default=None,
+                    help="run one extra workload alone and print its JSON object (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -425,6 +427,13 @@ def main() -> int:
     if not os.path.exists(rbm.LIB_PATH):
         from paper_1812_10575_amd import build as hip_build
         hip_build.build()
+
+    if args.only is not None:
+        torch.cuda.set_device(torch.device("cuda:0"))
+        fn = {"dyson_split": dyson_split, "wealth": wealth, "hamilton": hamilton, "rbmr": rbmr,
+              "ensemble": ensemble_rate}[args.only]
+        print(json.dumps({args.only: fn(args)}), flush=True)
+        return 0
 
     over = {} if args.p is None else {"p": args.p}
     w = rbm_inputs.params_of(args.workload, **over)

@@ -354,8 +354,8 @@ const char *rbm_last_error(void);
 #define RBM_RBMR_MAX_WINDOW (1u << 22)
 #define RBM_RBMR_MAX_ROUNDS 255
 
-/* Bytes of device workspace rbmr_run needs: 16 N + (p + 2) window +
- * 4 (rounds + 1), each part rounded up to 256. */
+/* Bytes of device workspace rbmr_run needs: 16 N (32 N for d = 3) +
+ * 8 window + 4 (rounds + 1), each part rounded up to 256. */
 rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes);
 
 /* Iterations k0 .. k0 + niter - 1 on d_x ([N][d] FP32 positions by particle

@@ -882,7 +882,7 @@ static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t round
     }
     if (rounds < 1 || rounds > RBM_RBMR_MAX_ROUNDS)
         return fail(RBM_ERR_INVALID, "rounds %d not in 1..%d", rounds, RBM_RBMR_MAX_ROUNDS);
-    *lay = rbm::rbmr_layout((uint32_t)prm->n, (uint32_t)prm->p, (uint32_t)window, (uint32_t)rounds);
+    *lay = rbm::rbmr_layout((uint32_t)prm->n, (uint32_t)prm->d, (uint32_t)window, (uint32_t)rounds);
     return RBM_OK;
 }
 

@@ -9,19 +9,25 @@
 // gives it, so the result depends neither on the window nor on the rounds
 // (bit for bit: an iteration's arithmetic is the same wherever it runs).
 //
-// One window:
+// A call packs the positions into per-particle records {two round tags,
+// position} (16 bytes for d <= 2, 32 for d = 3), so that a readiness check
+// and the update of a member touch one cache line, and unpacks them at the
+// end.  One window:
 //   k_rbmr_draw   draws every batch and marks each member with the round-0
-//                 tag of the iteration (64-bit atomic min)
+//                 tag of the iteration (32-bit atomic min)
 //   k_rbmr_round  round L: an iteration whose tag is still on all its
 //                 members runs; the others mark their members with the next
-//                 round's tag in the other tag array and queue themselves
+//                 round's tag in the other tag word and queue themselves
 //   k_rbmr_tail   one workgroup runs whatever is pending after the last
 //                 round, in iteration order (usually nothing: the depth of
 //                 a window of N/p random pairs is about 12)
-// Tag of iteration e (its offset in the window) in round g (counting up
-// over the call): (~g << 32) | e.  A later round's tags are below every
-// stale one, so the arrays need no reset between rounds, and within a round
-// the earliest iteration wins.  Round L reads tag array L mod 2 and writes
+// Batches are drawn again from the counter wherever they are needed (a few
+// ALU operations instead of a stored table read at random).  Tag of
+// iteration e (its offset in the window, < 2^22) in round g: ((1023 - g)
+// << 22) | e, g = 1 .. 1022 over a stretch of windows (the records are
+// refilled when g would pass 1022).  A later round's tags are below every
+// stale one, so the tags need no reset between rounds, and within a round
+// the earliest iteration wins.  Round L reads tag word L mod 2 and writes
 // the other, so what it reads was settled before it started.
 #include <hip/hip_runtime.h>
 
@@ -33,10 +39,16 @@ namespace {
 constexpr int TPB = 256;
 enum : uint32_t { STREAM_RBMR_DRAW = 2u, STREAM_RBMR_NOISE = 3u };
 
-__device__ __forceinline__ uint64_t tag_of(uint32_t g, uint32_t e)
+__device__ __forceinline__ uint32_t tag_of(uint32_t g, uint32_t e)
 {
-    return ((uint64_t)(~g) << 32) | e;
+    return ((1023u - g) << 22) | e;
 }
+
+template <int D>
+struct alignas(D <= 2 ? 16 : 32) RRec {
+    uint32_t tag[2];
+    float x[D <= 2 ? 2 : 6];
+};
 
 __device__ __forceinline__ uint4 rbmr_block(const RbmrArgs &a, uint64_t k, uint32_t sub, uint32_t stream)
 {
@@ -94,18 +106,14 @@ __device__ __forceinline__ void rbmr_noise(const RbmrArgs &a, uint64_t k, uint32
 
 // Iteration k on its members: forces at the positions it starts from, one
 // Euler-Maruyama step of the batch SDE (SPLIT: the exact pair flow of
-// K = x/|x|^2, then the field step), then the noise of its slots.
+// K = x/|x|^2, then the field step), then the noise of its slots.  Only the
+// position words of the records are written (other threads may be updating
+// the tag words of the same records).
 template <int D, int KERN, bool SPLIT>
 __device__ __forceinline__ void run_iteration(const RbmrArgs &a, uint64_t k, const uint32_t (&m)[RBMR_MAX_P],
-                                              float *__restrict__ x)
+                                              const float (&xs)[RBMR_MAX_P][D], RRec<D> *rec)
 {
-    float xs[RBMR_MAX_P][D], y[RBMR_MAX_P][D];
-#pragma unroll
-    for (int r = 0; r < RBMR_MAX_P; ++r)
-        if (r < (int)a.p) {
-#pragma unroll
-            for (int c = 0; c < D; ++c) xs[r][c] = x[(size_t)m[r] * D + c];
-        }
+    float y[RBMR_MAX_P][D];
     if constexpr (SPLIT) {
         pair_flow<D>(a.dt, xs[0], xs[1], y[0]);
         pair_flow<D>(a.dt, xs[1], xs[0], y[1]);
@@ -137,52 +145,82 @@ __device__ __forceinline__ void run_iteration(const RbmrArgs &a, uint64_t k, con
 #pragma unroll
                 for (int c = 0; c < D; ++c) y[r][c] = fmaf(a.ssd, z[c], y[r][c]);
             }
+            float *dst = rec[m[r]].x;
+            if constexpr (D == 2) {
+                *reinterpret_cast<float2 *>(dst) = make_float2(y[r][0], y[r][1]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < D; ++c) x[(size_t)m[r] * D + c] = y[r][c];
+                for (int c = 0; c < D; ++c) dst[c] = y[r][c];
+            }
         }
 }
 
-__device__ __forceinline__ void load_members(const RbmrArgs &a, const uint32_t *__restrict__ mem, uint32_t e,
-                                             uint32_t (&m)[RBMR_MAX_P])
+template <int D>
+__device__ __forceinline__ void load_positions(const RbmrArgs &a, const RRec<D> *rec, const uint32_t (&m)[RBMR_MAX_P],
+                                               float (&xs)[RBMR_MAX_P][D])
 {
 #pragma unroll
-    for (int r = 0; r < RBMR_MAX_P; ++r) m[r] = r < (int)a.p ? mem[(size_t)e * a.p + r] : 0u;
+    for (int r = 0; r < RBMR_MAX_P; ++r)
+        if (r < (int)a.p) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) xs[r][c] = rec[m[r]].x[c];
+        }
 }
 
-__global__ __launch_bounds__(TPB) void k_rbmr_fill(uint64_t *__restrict__ t, uint32_t n2)
+template <int D>
+__global__ __launch_bounds__(TPB) void k_rbmr_pack(uint32_t n, const float *__restrict__ x, RRec<D> *__restrict__ rec)
 {
     const uint32_t i = blockIdx.x * TPB + threadIdx.x;
-    if (i < n2) t[i] = ~(uint64_t)0;
+    if (i >= n) return;
+    RRec<D> r{};
+    r.tag[0] = r.tag[1] = 0xffffffffu;
+#pragma unroll
+    for (int c = 0; c < D; ++c) r.x[c] = x[(size_t)i * D + c];
+    rec[i] = r;
 }
 
+// Tags back to "untouched" (a new stretch of round numbers).
+template <int D>
+__global__ __launch_bounds__(TPB) void k_rbmr_retag(uint32_t n, RRec<D> *__restrict__ rec)
+{
+    const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+    if (i < n) *reinterpret_cast<uint2 *>(rec[i].tag) = make_uint2(0xffffffffu, 0xffffffffu);
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_rbmr_unpack(uint32_t n, const RRec<D> *__restrict__ rec, float *__restrict__ x)
+{
+    const uint32_t i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const RRec<D> r = rec[i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) x[(size_t)i * D + c] = r.x[c];
+}
+
+template <int D>
 __global__ __launch_bounds__(TPB) void k_rbmr_draw(RbmrArgs a, uint64_t kbase, uint32_t wcur, uint32_t g,
-                                                   uint32_t *__restrict__ mem, uint64_t *first,
-                                                   uint32_t *__restrict__ counts, uint32_t rounds)
+                                                   RRec<D> *rec, uint32_t *__restrict__ counts, uint32_t rounds)
 {
     const uint32_t e = blockIdx.x * TPB + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x <= rounds) counts[threadIdx.x] = 0u;
     if (e >= wcur) return;
     uint32_t m[RBMR_MAX_P];
     draw_members(a, kbase + e, m);
-    const uint64_t t = tag_of(g, e);
+    const uint32_t t = tag_of(g, e);
 #pragma unroll
     for (int r = 0; r < RBMR_MAX_P; ++r)
-        if (r < (int)a.p) {
-            mem[(size_t)e * a.p + r] = m[r];
-            atomicMin((unsigned long long *)&first[m[r]], (unsigned long long)t);
-        }
+        if (r < (int)a.p) atomicMin(&rec[m[r]].tag[0], t);
 }
 
 // Round L (tag g): L = 0 takes the whole window, later rounds the queue
 // lin[0 .. counts[L]).  Not-ready iterations go to lout / counts[L + 1].
 template <int D, int KERN, bool SPLIT>
 __global__ __launch_bounds__(TPB) void k_rbmr_round(RbmrArgs a, uint32_t L, uint32_t g, uint64_t kbase, uint32_t wcur,
-                                                    const uint32_t *__restrict__ mem, const uint64_t *__restrict__ tin,
-                                                    uint64_t *tout, const uint32_t *__restrict__ lin,
-                                                    uint32_t *__restrict__ lout, uint32_t *counts, float *__restrict__ x)
+                                                    RRec<D> *rec, const uint32_t *__restrict__ lin,
+                                                    uint32_t *__restrict__ lout, uint32_t *counts)
 {
     const uint32_t nin = L == 0 ? wcur : counts[L];
-    const uint64_t t = (uint64_t)(~g) << 32, t1 = (uint64_t)(~(g + 1u)) << 32;
+    const uint32_t wi = L & 1u, wo = wi ^ 1u;
     for (uint32_t base = blockIdx.x * TPB; base < nin; base += gridDim.x * TPB) {
         const uint32_t idx = base + threadIdx.x;
         bool pend = false;
@@ -190,17 +228,25 @@ __global__ __launch_bounds__(TPB) void k_rbmr_round(RbmrArgs a, uint32_t L, uint
         if (idx < nin) {
             e = L == 0 ? idx : lin[idx];
             uint32_t m[RBMR_MAX_P];
-            load_members(a, mem, e, m);
+            draw_members(a, kbase + e, m);
+            const uint32_t t = tag_of(g, e);
+            float xs[RBMR_MAX_P][D];
             bool ready = true;
 #pragma unroll
             for (int r = 0; r < RBMR_MAX_P; ++r)
-                if (r < (int)a.p) ready = ready && tin[m[r]] == (t | e);
+                if (r < (int)a.p) {
+                    const RRec<D> rr = rec[m[r]];
+                    ready = ready && rr.tag[wi] == t;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xs[r][c] = rr.x[c];
+                }
             if (ready) {
-                run_iteration<D, KERN, SPLIT>(a, kbase + e, m, x);
+                run_iteration<D, KERN, SPLIT>(a, kbase + e, m, xs, rec);
             } else {
+                const uint32_t t1 = tag_of(g + 1u, e);
 #pragma unroll
                 for (int r = 0; r < RBMR_MAX_P; ++r)
-                    if (r < (int)a.p) atomicMin((unsigned long long *)&tout[m[r]], (unsigned long long)(t1 | e));
+                    if (r < (int)a.p) atomicMin(&rec[m[r]].tag[wo], t1);
                 pend = true;
             }
         }
@@ -220,9 +266,8 @@ __global__ __launch_bounds__(TPB) void k_rbmr_round(RbmrArgs a, uint32_t L, uint
 // The iterations still pending after the last round, in iteration order, by
 // one thread (the workgroup finds the next one).
 template <int D, int KERN, bool SPLIT>
-__global__ __launch_bounds__(TPB) void k_rbmr_tail(RbmrArgs a, uint32_t rounds, uint64_t kbase,
-                                                   const uint32_t *__restrict__ mem, const uint32_t *__restrict__ list,
-                                                   const uint32_t *__restrict__ counts, float *__restrict__ x)
+__global__ __launch_bounds__(TPB) void k_rbmr_tail(RbmrArgs a, uint32_t rounds, uint64_t kbase, RRec<D> *rec,
+                                                   const uint32_t *__restrict__ list, const uint32_t *__restrict__ counts)
 {
     const uint32_t n = counts[rounds];
     if (n == 0) return;
@@ -245,8 +290,10 @@ __global__ __launch_bounds__(TPB) void k_rbmr_tail(RbmrArgs a, uint32_t rounds, 
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t m[RBMR_MAX_P];
-            load_members(a, mem, e, m);
-            run_iteration<D, KERN, SPLIT>(a, kbase + e, m, x);
+            draw_members(a, kbase + e, m);
+            float xs[RBMR_MAX_P][D];
+            load_positions<D>(a, rec, m, xs);
+            run_iteration<D, KERN, SPLIT>(a, kbase + e, m, xs, rec);
         }
         last = e;
         first_pass = false;
@@ -258,37 +305,34 @@ hipError_t launch_dk(const RbmrArgs &a, const RbmrLayout &lay, void *ws, float *
                      uint64_t niter, hipStream_t st)
 {
     char *w = static_cast<char *>(ws);
-    auto *tags = reinterpret_cast<uint64_t *>(w + lay.off_first);
-    uint64_t *tarr[2] = {tags, tags + a.n};
-    auto *mem = reinterpret_cast<uint32_t *>(w + lay.off_mem);
+    auto *rec = reinterpret_cast<RRec<D> *>(w + lay.off_rec);
     uint32_t *lists[2] = {reinterpret_cast<uint32_t *>(w + lay.off_list0),
                           reinterpret_cast<uint32_t *>(w + lay.off_list1)};
     auto *counts = reinterpret_cast<uint32_t *>(w + lay.off_counts);
     const uint32_t R = lay.rounds;
-    const uint32_t n2 = 2u * a.n;
-    uint32_t g = 0;
-    bool filled = false;
+    const dim3 gn((a.n + TPB - 1) / TPB);
+    hipLaunchKernelGGL(k_rbmr_pack<D>, gn, dim3(TPB), 0, st, a.n, x, rec);
+    uint32_t g = 1;
     for (uint64_t done = 0; done < niter;) {
         const uint32_t wcur = (uint32_t)((niter - done) < lay.window ? (niter - done) : lay.window);
-        if (!filled || (uint64_t)g + R + 2u >= 0xffffffffull) {
-            hipLaunchKernelGGL(k_rbmr_fill, dim3((n2 + TPB - 1) / TPB), dim3(TPB), 0, st, tags, n2);
-            g = 0;
-            filled = true;
+        if (g + R + 1u > 1022u) {
+            hipLaunchKernelGGL(k_rbmr_retag<D>, gn, dim3(TPB), 0, st, a.n, rec);
+            g = 1;
         }
         const uint32_t g0 = (wcur + TPB - 1) / TPB;
-        hipLaunchKernelGGL(k_rbmr_draw, dim3(g0), dim3(TPB), 0, st, a, kbase + done, wcur, g, mem, tarr[0], counts, R);
+        hipLaunchKernelGGL(k_rbmr_draw<D>, dim3(g0), dim3(TPB), 0, st, a, kbase + done, wcur, g, rec, counts, R);
         for (uint32_t L = 0; L < R; ++L) {
             uint32_t grid = L == 0 ? g0 : g0 >> L;
             if (grid < 64u) grid = g0 < 64u ? g0 : 64u;
             hipLaunchKernelGGL((k_rbmr_round<D, KERN, SPLIT>), dim3(grid), dim3(TPB), 0, st, a, L, g + L, kbase + done,
-                               wcur, mem, tarr[L & 1u], tarr[(L + 1u) & 1u], lists[L & 1u], lists[(L + 1u) & 1u],
-                               counts, x);
+                               wcur, rec, lists[L & 1u], lists[(L + 1u) & 1u], counts);
         }
-        hipLaunchKernelGGL((k_rbmr_tail<D, KERN, SPLIT>), dim3(1), dim3(TPB), 0, st, a, R, kbase + done, mem,
-                           lists[R & 1u], counts, x);
+        hipLaunchKernelGGL((k_rbmr_tail<D, KERN, SPLIT>), dim3(1), dim3(TPB), 0, st, a, R, kbase + done, rec,
+                           lists[R & 1u], counts);
         g += R + 1u;
         done += wcur;
     }
+    hipLaunchKernelGGL(k_rbmr_unpack<D>, gn, dim3(TPB), 0, st, a.n, rec, x);
     return hipGetLastError();
 }
 
@@ -311,16 +355,14 @@ size_t al256(size_t v)
 
 }  // namespace
 
-RbmrLayout rbmr_layout(uint32_t n, uint32_t p, uint32_t window, uint32_t rounds)
+RbmrLayout rbmr_layout(uint32_t n, uint32_t d, uint32_t window, uint32_t rounds)
 {
     RbmrLayout l{};
     l.window = window;
     l.rounds = rounds;
     size_t o = 0;
-    l.off_first = o;
-    o = al256(o + (size_t)2 * n * sizeof(uint64_t));
-    l.off_mem = o;
-    o = al256(o + (size_t)window * p * sizeof(uint32_t));
+    l.off_rec = o;
+    o = al256(o + (size_t)n * (d <= 2 ? 16u : 32u));
     l.off_list0 = o;
     o = al256(o + (size_t)window * sizeof(uint32_t));
     l.off_list1 = o;

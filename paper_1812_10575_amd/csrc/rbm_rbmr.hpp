@@ -23,14 +23,14 @@ struct RbmrArgs {
     float ssd;        // sigma sqrt(dt)
 };
 
-// Workspace: two tag arrays [n] (uint64), the members of a window
-// [window][p], two queues [window] and the round counters [rounds + 1].
+// Workspace: the particle records [n] (16 bytes for d <= 2, 32 for d = 3),
+// two queues [window] and the round counters [rounds + 1].
 struct RbmrLayout {
-    size_t off_first, off_mem, off_list0, off_list1, off_counts, bytes;
+    size_t off_rec, off_list0, off_list1, off_counts, bytes;
     uint32_t window, rounds;
 };
 
-RbmrLayout rbmr_layout(uint32_t n, uint32_t p, uint32_t window, uint32_t rounds);
+RbmrLayout rbmr_layout(uint32_t n, uint32_t d, uint32_t window, uint32_t rounds);
 
 // Iterations kbase .. kbase + niter - 1 on the positions x ([n][d], by id).
 hipError_t rbmr_launch(const RbmrArgs &a, int d, int kernel, const RbmrLayout &lay, void *ws, float *x,
