@@ -126,7 +126,9 @@ Plan make_plan(const rbm_params *prm)
     if (pl.n <= RBM_SINGLE_CAP) {
         pl.nbuck = pl.nb1 = 1;
     } else {
-        const uint32_t target = (pl.n + RBM_BUCKET_MEAN - 1) / RBM_BUCKET_MEAN;
+        // at most RBM_MAX_FINE fine buckets (the one-workgroup scan of the
+        // bucket totals) and so at most RBM_MAX_FINE / 2^shift coarse ones
+        const uint32_t target = std::min<uint32_t>((pl.n + RBM_BUCKET_MEAN - 1) / RBM_BUCKET_MEAN, RBM_MAX_FINE);
         const uint32_t per = 1u << RBM_SPLIT_SHIFT;
         if (target <= per) {
             pl.shift = 0;
@@ -139,6 +141,7 @@ Plan make_plan(const rbm_params *prm)
             const double mean = (double)pl.n / pl.nb1;
             pl.jmax = (uint32_t)std::ceil((mean + 16.0 * std::sqrt(mean) + 64.0) / RBM_CHUNK);
         }
+        pl.cap = (uint64_t)pl.n <= (uint64_t)pl.nbuck * RBM_BUCKET_MEAN ? RBM_SORT_CAP : RBM_SORT_CAP_BIG;
         pl.ntiles = (pl.n + RBM_TILE - 1) / RBM_TILE;
         // about 128 key-count tiles, a multiple of 4 slots each
         uint32_t tf = (pl.n + 127) / 128;

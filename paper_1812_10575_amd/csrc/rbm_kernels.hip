@@ -4,7 +4,7 @@
 // One step m, with the particles held as records (x, id) in "slot" order
 // (the order left by the previous step).  Slot k draws the PERM word w_k; the
 // key (w_k << 32 | id) orders the particles.  The word range is cut into B
-// equal "fine buckets", f = floor(w B / 2^32) (about 1024 records each),
+// equal "fine buckets", f = floor(w B / 2^32) (about 960 records each),
 // grouped 2^shift at a time into coarse buckets.
 //
 //   k_key_count      per tile of slots, fine-bucket histogram of the words
@@ -12,11 +12,11 @@
 //                    the state)
 //   k_key_colsum     fine-bucket totals
 //   k_key_starts     fine and coarse bucket starts, run cursors
-//   k_scatter_coarse a tile's 16K records, held in registers, go to their
+//   k_scatter_coarse a tile's 8K records, held in registers, go to their
 //                    coarse buckets; each (tile, bucket) run is reserved with
 //                    one atomic and written through an LDS reorder so that
 //                    lanes store to consecutive addresses
-//   k_split          each 16K-record chunk of a coarse bucket goes to its
+//   k_split          each 8K-record chunk of a coarse bucket goes to its
 //                    fine buckets the same way
 //   k_sort_step      one workgroup per fine bucket: order it in LDS by the
 //                    unique key, evaluate the batch forces of eq. (2.3) for
@@ -120,8 +120,10 @@ __device__ __forceinline__ uint32_t wave0_exclusive_scan(const uint32_t *a, uint
 // ---------------------------------------------------------------------------
 constexpr uint32_t TILE = RBM_TILE;    // slots per coarse-scatter workgroup
 constexpr uint32_t CHUNK = RBM_CHUNK;  // records per split workgroup
-constexpr int LVL_TPB = RBM_LVL_TPB;   // 16 records per thread
-constexpr int LVL_P = 16;
+constexpr int LVL_TPB = RBM_LVL_TPB;
+constexpr int LVL_P = RBM_LVL_P;       // records per thread
+constexpr int LVL_RPT = RBM_LVL_RPT;   // records per thread and LDS round
+static_assert(LVL_P % 4 == 0 && LVL_P % LVL_RPT == 0, "staging rounds must divide the records per thread");
 constexpr int LVL_NB = 256;            // largest digit count of a level
 
 __global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, uint32_t *cnt)
@@ -237,16 +239,17 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
 }
 
 // ---------------------------------------------------------------------------
-// staged writes: a workgroup's 16K records (in registers) go to per-digit
-// runs.  Each digit's run is reserved once with one global atomic on the
-// digit's cursor; the records are then ordered by digit in LDS, 4096 at a
-// time, so that consecutive lanes store to consecutive addresses.
+// staged writes: a workgroup's LVL_P x LVL_TPB = 8K records (in registers) go
+// to per-digit runs.  Each digit's run is reserved once with one global
+// atomic on the digit's cursor; the records are then ordered by digit in LDS,
+// LVL_RPT x LVL_TPB at a time, so that consecutive lanes store to consecutive
+// addresses.
 // ---------------------------------------------------------------------------
 template <int D>
 struct StageLds {
-    Rec<D> rec[4 * LVL_TPB];
-    uint32_t w[4 * LVL_TPB];
-    uint16_t dig[4 * LVL_TPB];
+    Rec<D> rec[LVL_RPT * LVL_TPB];
+    uint32_t w[LVL_RPT * LVL_TPB];
+    uint16_t dig[LVL_RPT * LVL_TPB];
     uint32_t cnt[LVL_NB];   // round counts / tile counts
     uint32_t start[LVL_NB]; // round starts
     uint32_t gbase[LVL_NB]; // next global position of each digit
@@ -271,13 +274,13 @@ __device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const 
         L.gbase[d] = L.cnt[d] ? atomicAdd(&gcur[d], L.cnt[d]) : 0u;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < LVL_P / 4; ++r) {
+    for (int r = 0; r < LVL_P / LVL_RPT; ++r) {
         for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.cnt[d] = 0;
         __syncthreads();
-        uint32_t lr[4];
+        uint32_t lr[LVL_RPT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = 4 * r + q;
+        for (int q = 0; q < LVL_RPT; ++q) {
+            const int k = LVL_RPT * r + q;
             lr[q] = (uint32_t)k < nact ? atomicAdd(&L.cnt[(fine_of(w[k], nbuck) >> shift) & mask], 1u) : 0u;
         }
         __syncthreads();
@@ -285,8 +288,8 @@ __device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const 
         if (tid < 64) total = wave0_exclusive_scan(L.cnt, L.start, ndig);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = 4 * r + q;
+        for (int q = 0; q < LVL_RPT; ++q) {
+            const int k = LVL_RPT * r + q;
             if ((uint32_t)k < nact) {
                 const uint32_t d = (fine_of(w[k], nbuck) >> shift) & mask;
                 const uint32_t slot = L.start[d] + lr[q];
@@ -314,7 +317,8 @@ __device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const 
     }
 }
 
-// Coarse scatter: tile of 16K slots.  Thread t holds slots 4(t + 1024 g) + j.
+// Coarse scatter: tile of LVL_P x LVL_TPB slots.  Thread t holds slots
+// 4(t + LVL_TPB g) + j.
 // Records of a partial last tile are packed so that the first nact of each
 // thread are the valid ones.
 template <int D>
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, u
     if (lo == hi) return;
     float rx[LVL_P][D];
     uint32_t rid[LVL_P], w[LVL_P];
-    // thread t holds records lo + t + 1024 k: the valid ones are a prefix in k
+    // thread t holds records lo + t + LVL_TPB k: the valid ones are a prefix in k
     uint32_t nact = 0;
 #pragma unroll
     for (int k = 0; k < LVL_P; ++k) {
@@ -419,87 +423,16 @@ __device__ __forceinline__ void finish(const StepArgs &s, float (&x)[D], float (
     dst[r] = o;
 }
 
-// A batch of exactly P members b[0..P) at ranks bs..bs+P: every unordered
-// pair is evaluated once and applied with both signs (K is odd).
-template <int D, int KERN, int P>
-__device__ __forceinline__ void batch_fast(const StepArgs &s, const Rec<D> *b, uint32_t bs,
-                                           Rec<D> *dst, float *__restrict__ fout)
-{
-    float x[P][D], f[P][D];
-    uint32_t id[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const Rec<D> r = b[i];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            x[i][c] = r.x[c];
-            f[i][c] = 0.0f;
-        }
-        id[i] = r.id;
-    }
-    if constexpr (P == 2) {
-        if (pair_flow_scheme(s) && !fout) {
-            // the pair moves by its exact flow, then the external field acts
-            float y[2][D], zero[D] = {};
-            if (s.scheme == 1) {
-                pair_flow<D>(s.dt, x[0], x[1], y[0]);
-                pair_flow<D>(s.dt, x[1], x[0], y[1]);
-            } else {
-                pair_flow_linear<D>(s.flowc, x[0], x[1], y[0]);
-                pair_flow_linear<D>(s.flowc, x[1], x[0], y[1]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i) finish<D>(s, y[i], zero, id[i], bs + i, dst, fout);
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-#pragma unroll
-        for (int j = i + 1; j < P; ++j) {
-            constexpr int DK = kdim<D, KERN>();
-            float dx[DK], r2 = 0.0f;
-#pragma unroll
-            for (int c = 0; c < DK; ++c) {
-                dx[c] = x[i][c] - x[j][c];
-                r2 = fmaf(dx[c], dx[c], r2);
-            }
-            const float sc = pair_scale<KERN>(r2, s.a);
-#pragma unroll
-            for (int c = 0; c < DK; ++c) {
-                f[i][c] = fmaf(sc, dx[c], f[i][c]);
-                f[j][c] = fmaf(-sc, dx[c], f[j][c]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) f[i][c] *= s.inv_p1;
-        finish<D>(s, x[i], f[i], id[i], bs + i, dst, fout);
-    }
-}
-
-// LDS slot of the record at global rank r in a bucket starting at lo: one
-// empty slot follows every P ranks (P > 0), so that threads reading whole
-// batches of P records see a lane stride of 4(P + 1) words, which spreads
-// them over all banks.
-template <int P>
-struct Pad {
+// LDS slot of the record at global rank r in a bucket starting at lo.
+struct Slot {
     uint32_t lo;
-    __device__ __forceinline__ uint32_t operator()(uint32_t r) const
-    {
-        if constexpr (P > 0)
-            return (r - lo) + r / P - lo / P;
-        else
-            return r - lo;
-    }
+    __device__ __forceinline__ uint32_t operator()(uint32_t r) const { return r - lo; }
 };
 
 // Member r of the batch of ranks [bs, bs + sz) (any size): its force by
 // direct summation.
-template <int D, int KERN, int P>
-__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *srec, Pad<P> pad,
+template <int D, int KERN>
+__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *srec, Slot pad,
                                                uint32_t bs, uint32_t sz, uint32_t r, Rec<D> *dst,
                                                float *__restrict__ fout)
 {
@@ -518,6 +451,46 @@ __device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *
     finish<D>(s, xi, f, me.id, r, dst, fout);
 }
 
+// Member r of a batch of exactly PM members starting at rank bs: its force
+// by direct summation over the batch in rank order, with the member loop
+// unrolled.  One thread per record keeps the registers per thread low (64 at
+// d = 3, six workgroups per CU); a thread per batch evaluating each pair once
+// needed 98 and fitted four.  The sum over j is in the same order either way.
+template <int D, int KERN, int PM>
+__device__ __forceinline__ void member_fixed(const StepArgs &s, const Rec<D> *srec, Slot pad, uint32_t bs,
+                                             uint32_t r, Rec<D> *dst, float *__restrict__ fout)
+{
+    const Rec<D> me = srec[pad(r)];
+    float xi[D], f[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        xi[c] = me.x[c];
+        f[c] = 0.0f;
+    }
+    if constexpr (PM == 2) {
+        if (pair_flow_scheme(s) && !fout) {
+            // the pair moves by its exact flow; the partner's thread makes the
+            // same operations with the arguments swapped
+            const float *xj = srec[pad(bs + (r == bs ? 1u : 0u))].x;
+            float y[D];
+            if (s.scheme == 1)
+                pair_flow<D>(s.dt, xi, xj, y);
+            else
+                pair_flow_linear<D>(s.flowc, xi, xj, y);
+            finish<D>(s, y, f, me.id, r, dst, fout);
+            return;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PM; ++j) {
+        const uint32_t rj = bs + (uint32_t)j;
+        if (rj != r) add_pair<D, KERN>(xi, srec[pad(rj)].x, s.a, f);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) f[c] *= s.inv_p1;
+    finish<D>(s, xi, f, me.id, r, dst, fout);
+}
+
 // One workgroup per fine bucket [lo, hi) (SINGLE: the whole system, read
 // from the slot-ordered state, PERM words drawn here).
 //   1. load: records stay in registers; words and ids go to LDS; each record
@@ -526,12 +499,12 @@ __device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *
 //   2. exclusive scan of the sub-bucket counts; member lists per sub-bucket
 //   3. rank = sub-bucket start + members with a smaller (w, id) key
 //   4. records written to LDS in sorted order (reusing the ordering bytes)
-//   5. batches inside the bucket: P > 0, one thread per batch of P (pairs
-//      once, antisymmetric); P = 0, one thread per record.  Records of cut
-//      batches go to dst unchanged for k_fixup.
+//   5. batches inside the bucket, one thread per record (PM > 0: p = PM,
+//      the member loop unrolled).  Records of cut batches go to dst
+//      unchanged for k_fixup.
 // fout != nullptr: forces only (by id); dst gets only the cut batches.
 // SORTONLY: every record is written to dst at its rank, nothing else.
-template <int D, int KERN, int P, bool SINGLE, int TPB, int CAP, int SBITS, bool SORTONLY = false>
+template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SBITS, bool SORTONLY = false, int PM = 0>
 __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src,
                                                    const uint32_t *__restrict__ wsrc,
                                                    const uint32_t *__restrict__ bstart,
@@ -542,7 +515,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     constexpr int E = (CAP + TPB - 1) / TPB;
     static_assert(S % TPB == 0, "sub-bucket count must be a multiple of the block");
     constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
-    constexpr size_t REC_BYTES = (size_t)(CAP + (P > 0 ? CAP / P + 2 : 0)) * sizeof(Rec<D>);
+    constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
     __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
     __shared__ uint32_t scan_tmp[TPB / 64];
     uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
@@ -628,7 +601,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     }
     __syncthreads();
     // 4. sorted records
-    const Pad<P> pad{lo};
+    const Slot pad{lo};
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
@@ -663,24 +636,20 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         if (r < ins_lo || r >= ins_hi) dst[r] = srec[pad(r)];
     }
     if (!any) return;
-    if constexpr (P > 0) {
-        const uint32_t nq = (uint32_t)(q_last - q_first + 1);
-        for (uint32_t qq = tid; qq < nq; qq += TPB) {
-            const uint32_t q = (uint32_t)q_first + qq;
-            const uint32_t bs = q * p;
-            const uint32_t sz = (q == s.nbat - 1) ? s.n - bs : p;
-            if (sz == (uint32_t)P) {
-                batch_fast<D, KERN, P>(s, srec + pad(bs), bs, dst, fout);
-            } else {
-                for (uint32_t i = 0; i < sz; ++i)
-                    member_generic<D, KERN, P>(s, srec, pad, bs, sz, bs + i, dst, fout);
-            }
-        }
-    } else {
-        for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
+    for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
+        if constexpr (PM > 0) {
+            // p == PM: batch geometry with a compile-time divisor
+            uint32_t q = r / (uint32_t)PM;
+            if (q > s.nbat - 1) q = s.nbat - 1;
+            const uint32_t bs = q * (uint32_t)PM;
+            if (q != s.nbat - 1 || s.n - bs == (uint32_t)PM)
+                member_fixed<D, KERN, PM>(s, srec, pad, bs, r, dst, fout);
+            else
+                member_generic<D, KERN>(s, srec, pad, bs, s.n - bs, r, dst, fout);
+        } else {
             uint32_t bs, be;
             batch_of(s, r, bs, be);
-            member_generic<D, KERN, P>(s, srec, pad, bs, be - bs, r, dst, fout);
+            member_generic<D, KERN>(s, srec, pad, bs, be - bs, r, dst, fout);
         }
     }
 }
@@ -923,7 +892,9 @@ constexpr int SINGLE_CAP = RBM_SINGLE_CAP;
 constexpr int SINGLE_SBITS = 11;
 constexpr int SORT_TPB = 256;
 constexpr int SORT_CAP = RBM_SORT_CAP;
+constexpr int SORT_CAP_BIG = RBM_SORT_CAP_BIG;
 constexpr int SORT_SBITS = 10;
+static_assert((RBM_MAX_FINE >> RBM_SPLIT_SHIFT) <= LVL_NB, "coarse buckets beyond the staging arrays");
 constexpr int DIRECT_TPB = 256;
 
 inline void mark(hipEvent_t *ev, int i, hipStream_t st)
@@ -971,7 +942,7 @@ hipError_t keys_impl(const Plan &pl, const StepArgs &s, uint32_t count, void *ws
                            pl.nbuck, q.kcnt, q.ftot);
         mark(ev, 2, st);
         hipLaunchKernelGGL(k_key_starts, dim3(count), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
-                           (uint32_t)SORT_CAP, q.ftot, q.fstart, q.fcur, q.cstart, q.ccur, flags);
+                           pl.cap, q.ftot, q.fstart, q.fcur, q.cstart, q.ccur, flags);
     } else {
         mark(ev, 1, st);
         mark(ev, 2, st);
@@ -997,7 +968,7 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     hipError_t e = hipSuccess;
     if (pl.nbuck == 1) {
         for (int i = 4; i <= 5; ++i) mark(ev, i, st);
-        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
+        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
                            dim3(1), dim3(SINGLE_TPB), 0, st, s, state, nullptr, nullptr, sorted,
                            nullptr, flags);
     } else {
@@ -1023,9 +994,14 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
             mark(ev, 4, st);
         }
         mark(ev, 5, st);
-        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, 0, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>),
-                           dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
-                           nullptr, flags);
+        if (pl.cap == (uint32_t)SORT_CAP)
+            hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>),
+                               dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
+                               nullptr, flags);
+        else
+            hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, false, SORT_TPB, SORT_CAP_BIG, SORT_SBITS, true>),
+                               dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
+                               nullptr, flags);
     }
     // phase A over the key-ordered records (their noise is in): c of every
     // particle, kept for phase B, and S; timed with the batch phase
@@ -1048,8 +1024,8 @@ void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const
                  const uint32_t *wsrc, const uint32_t *bstart, Rec<D> *dst, float *fout,
                  uint32_t *flags)
 {
-#define RBM_SORT(PP)                                                                              \
-    hipLaunchKernelGGL((k_sort_step<D, KERN, PP, SINGLE, TPB, CAP, SB>), grid, dim3(TPB), 0, st, s, \
+#define RBM_SORT(PMM)                                                                                   \
+    hipLaunchKernelGGL((k_sort_step<D, KERN, SINGLE, TPB, CAP, SB, false, PMM>), grid, dim3(TPB), 0, st, s, \
                        src, wsrc, bstart, dst, fout, flags)
     switch (p) {
     case 2: RBM_SORT(2); break;
@@ -1108,8 +1084,12 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         mark(ev, 4, st);
         mark(ev, 5, st);
     }
-    launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
-                                                                fstart, dst, fout, flags);
+    if (pl.cap == (uint32_t)SORT_CAP)
+        launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
+                                                                    fstart, dst, fout, flags);
+    else  // the largest systems: 1024-record buckets, the generic batch loop
+        hipLaunchKernelGGL((k_sort_step<D, KERN, false, SORT_TPB, SORT_CAP_BIG, SORT_SBITS, false, 0>),
+                           dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, dst, fout, flags);
     mark(ev, 6, st);
     hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, fout);
     mark(ev, 7, st);

@@ -11,16 +11,25 @@
 // Capacity of the one-workgroup path (the whole system in LDS, 75 KB at
 // d = 3).
 #define RBM_SINGLE_CAP 2816
-// Fine buckets average RBM_BUCKET_MEAN records; a sort workgroup holds up to
-// RBM_SORT_CAP (15 standard deviations above the mean) in 40 KB of LDS, so
-// four workgroups share a CU.
-#define RBM_BUCKET_MEAN 1024
-#define RBM_SORT_CAP 1520
+// Fine buckets average at most RBM_BUCKET_MEAN records (957 at N = 2^24)
+// while that needs at most RBM_MAX_FINE buckets (N <= 31,457,280); a sort
+// workgroup then holds up to RBM_SORT_CAP (10 standard deviations above the
+// mean; a fuller bucket is reported, not dropped) in 20 KB of LDS, so eight
+// workgroups share a CU.  Above that N the RBM_MAX_FINE buckets average up to
+// 1024 records and the sort holds up to RBM_SORT_CAP_BIG (15 standard
+// deviations).
+#define RBM_BUCKET_MEAN 960
+#define RBM_SORT_CAP 1270
+#define RBM_SORT_CAP_BIG 1520
 #define RBM_KEY_SETS 8
 #define RBM_MAX_FINE 32768
+// Scatter and split workgroups: RBM_LVL_TPB threads holding RBM_LVL_P
+// records each, staged through LDS RBM_LVL_RPT per thread at a time.
 #define RBM_LVL_TPB 512
-#define RBM_TILE (16 * RBM_LVL_TPB)
-#define RBM_CHUNK (16 * RBM_LVL_TPB)
+#define RBM_LVL_P 16
+#define RBM_LVL_RPT 4
+#define RBM_TILE (RBM_LVL_P * RBM_LVL_TPB)
+#define RBM_CHUNK (RBM_LVL_P * RBM_LVL_TPB)
 #define RBM_SPLIT_SHIFT 7
 
 namespace rbm {
@@ -39,6 +48,7 @@ struct Plan {
     uint32_t tilef;   // slots per key-count tile
     uint32_t ntf;     // key-count tiles
     uint32_t kb;      // key sets: the key passes of up to kb consecutive steps run as one launch
+    uint32_t cap;     // records a sort workgroup holds: RBM_SORT_CAP or RBM_SORT_CAP_BIG
     size_t rec_bytes;
     size_t off_state, off_scratch, off_stage1, off_w1, off_stage2, off_w2;
     size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;

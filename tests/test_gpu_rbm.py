@@ -236,11 +236,14 @@ def test_full_size_attrep3d_step():
     assert e_rel(x10, xo) <= 1e-5
 
 
-def test_largest_supported_size():
-    """N = 2^25 (the largest the plan supports: 32768 fine buckets), p = 3
-    with a remainder of 2: permutation bit-exact and e1 <= 1e-5."""
-    w = rbm_inputs.params_of("dyson1d-n2^20-p2", n=1 << 25, p=3)
-    say("max size", w["n"])
+@pytest.mark.parametrize("n,p", [(1 << 25, 3), (31457280, 8), (31457281, 8)])
+def test_largest_supported_size(n, p):
+    """N = 2^25 (the largest the plan supports: 32768 fine buckets of 1024
+    records on average, the larger sort capacity), p = 3 with a remainder of
+    2; and the two sides of the largest N whose buckets average at most 960
+    records: permutation bit-exact and e1 <= 1e-5."""
+    w = rbm_inputs.params_of("dyson1d-n2^20-p2", n=n, p=p)
+    say("max size", w["n"], w["p"])
     ctx, x0 = start(w)
     rbm.rbm_step(ctx)
     rbm.rbm_check(ctx)
