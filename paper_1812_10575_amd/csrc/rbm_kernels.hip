@@ -1017,8 +1017,8 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     return hipGetLastError();
 }
 
-// The sort kernel specialised on the batch size (one thread per batch) for
-// the common sizes; any other p takes the one-thread-per-record form.
+// The sort kernel with the batch size fixed at compile time (unrolled member
+// loop) for the common sizes; any other p takes the runtime loop.
 template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB>
 void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const Rec<D> *src,
                  const uint32_t *wsrc, const uint32_t *bstart, Rec<D> *dst, float *fout,
