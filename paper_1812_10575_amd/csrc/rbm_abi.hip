@@ -278,12 +278,25 @@ const char *rbm_last_error(void)
     return g_err.c_str();
 }
 
+// The plan stays within the limits the step kernels are built for: the
+// one-workgroup scan of the fine-bucket totals and the staging arrays of the
+// coarse digits.
+static rbm_status check_plan(const Plan &pl)
+{
+    if (pl.nbuck > RBM_MAX_FINE || pl.nb1 > (RBM_MAX_FINE >> RBM_SPLIT_SHIFT))
+        return fail(RBM_ERR_UNSUPPORTED, "N = %u needs %u fine buckets (at most %d)", pl.n, pl.nbuck, RBM_MAX_FINE);
+    return RBM_OK;
+}
+
 rbm_status rbm_workspace_size(const rbm_params *prm, size_t *bytes)
 {
     rbm_status st = check_params(prm);
     if (st != RBM_OK) return st;
     if (!bytes) return fail(RBM_ERR_INVALID, "bytes is NULL");
-    *bytes = make_plan(prm).total;
+    const Plan pl = make_plan(prm);
+    st = check_plan(pl);
+    if (st != RBM_OK) return st;
+    *bytes = pl.total;
     return RBM_OK;
 }
 
@@ -295,6 +308,8 @@ rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_
     if (!d_x0 || !d_ws || !out) return fail(RBM_ERR_INVALID, "NULL pointer argument");
     if (step0 < 0 || step0 > 0xffffffffLL) return fail(RBM_ERR_INVALID, "step0 out of range");
     const Plan pl = make_plan(prm);
+    st = check_plan(pl);
+    if (st != RBM_OK) return st;
     if (ws_bytes < pl.total)
         return fail(RBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, pl.total);
     if (((uintptr_t)d_ws & 255u) != 0) return fail(RBM_ERR_WORKSPACE, "workspace not 256-byte aligned");

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1812_10575_amd as rbm
@@ -68,6 +69,18 @@ def test_bad_parameters_are_rejected(kw, status):
         rbm.rbm_workspace_size(P(**kw))
     assert ei.value.status == status
     assert rbm.rbm_last_error()
+
+
+def test_plan_fits_the_kernels_at_every_size():
+    """Every supported N gets a bucket plan inside the limits the step
+    kernels are built for (at most 32768 fine buckets; the library refuses a
+    plan beyond them): the sizes around the bucket-size switch at
+    31,457,280, the largest N, powers of two and a log-spaced sweep."""
+    ns = {2817, 122880, 122881, 31457280, 31457281, (1 << 25) - 1, 1 << 25}
+    ns |= {1 << k for k in range(12, 26)}
+    ns |= {int(v) for v in np.geomspace(3000, 1 << 25, 200)}
+    for n in sorted(ns):
+        assert rbm.rbm_workspace_size(P(n=n)) >= 3 * 16 * n, n
 
 
 def test_large_p_is_fine_when_one_workgroup_holds_the_system():
