@@ -480,6 +480,29 @@ def test_hamilton_hundred_steps_and_direct_verlet():
     assert e_rel(f, ora.direct_forces(op(w), x.astype(np.float64))) <= 1e-5
 
 
+@pytest.mark.parametrize("n,p", [(2000, 2000), (50001, 5)])
+def test_hamilton_in_a_harmonic_field(n, p):
+    """b(x) = -beta x (Appendix A) with beta = 2, including p = N (one batch,
+    the one-workgroup path): three steps against the oracle, and p = N
+    equals the fully coupled Verlet step."""
+    w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=n, p=p, beta=2.0)
+    ctx, x0 = start(w)
+    o = op(w)
+    for m in range(3):
+        xm, sm = state(ctx)
+        rbm.rbm_step(ctx)
+        x1, s1 = state(ctx)
+        xo, so = ora.rbm_step(o, p, m, xm.astype(np.float64), sm)
+        assert np.array_equal(s1, so), m
+        assert e_rel(x1, xo) <= 1e-5, (m, e_rel(x1, xo))
+    if p == n:
+        ctx, _ = start(w)
+        rbm.rbm_step(ctx)
+        x1, _ = state(ctx)
+        xd = rbm.direct_step(gp(w), torch.from_numpy(x0).cuda(), 0).cpu().numpy()
+        assert e_rel(x1, xd) <= 1e-5
+
+
 def test_hamilton_rejects_noise_and_other_d():
     for over in ({"sigma": 0.1}, {"d": 1}, {"d": 3}, {"kparam": 0.0}):
         w = rbm_inputs.params_of("hamilton1d-n2^20-p2", n=1024, **over)

@@ -57,6 +57,8 @@ CASES = [
     ("attrep3d-n2^24-p8", {"n": 100003, "p": 7}, "attrep3d", 1),
     ("attrep3d-n2^24-p8", {"n": 65536, "p": 3}, "attrep3d", 2),
     ("dysonrbmr1d-n2^20-p2", {"n": 30000, "sigma": 1.0 / math.sqrt(30000)}, "semicircle2", 3),
+    ("dysonrbmr1d-n2^20-p2", {"n": 20001, "d": 3, "sigma": 0.05}, "attrep3d", 2),
+    ("dysonrbmr1d-n2^20-p2", {"n": 4097, "d": 2, "sigma": 0.0}, "gauss2d", 3),
 ]
 
 
