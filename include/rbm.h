@@ -348,8 +348,10 @@ const char *rbm_last_error(void);
  * rbm_params: d 1..3, kernel RBM_K_GAUSS .. RBM_K_COULOMB_SPLIT (the latter
  * with p = 2 and kparam = 0), 2 <= p <= min(N, RBM_RBMR_MAX_P), cv = 0.
  * window: iterations per round schedule, 0 for N/p (at most
- * RBM_RBMR_MAX_WINDOW).  rounds: parallel rounds per window before the rest
- * runs in order on one workgroup, 0 for (10 + 3p) ceil(window p / N). */
+ * RBM_RBMR_MAX_WINDOW).  rounds: rounds per window across the whole GPU;
+ * one workgroup then continues the rounds for what is left (up to 64 more),
+ * then runs any rest in order; 0 for (4 + 2p) ceil(window p / N), one more
+ * above N = 2^22. */
 #define RBM_RBMR_MAX_P 8
 #define RBM_RBMR_MAX_WINDOW (1u << 22)
 #define RBM_RBMR_MAX_ROUNDS 255

@@ -894,9 +894,12 @@ static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t round
     if (window < 1 || window > RBMR_MAX_WINDOW)
         return fail(RBM_ERR_INVALID, "window %lld not in 1..%u", (long long)window, RBMR_MAX_WINDOW);
     if (rounds == 0) {
-        // about twice the usual depth of a window (touches per particle c = window p / N)
+        // rounds across the GPU until a few hundred iterations of a window of
+        // N/p are left for the finishing workgroup (touches per particle
+        // c = window p / N; the depth grows with c and, slowly, with N)
         const int64_t c = (window * prm->p + prm->n - 1) / prm->n;
-        rounds = (int32_t)std::min<int64_t>((10 + 3 * prm->p) * c, RBM_RBMR_MAX_ROUNDS);
+        const int64_t extra = prm->n > (1 << 22) ? 1 : 0;
+        rounds = (int32_t)std::min<int64_t>((4 + 2 * prm->p) * c + extra, RBM_RBMR_MAX_ROUNDS);
     }
     if (rounds < 1 || rounds > RBM_RBMR_MAX_ROUNDS)
         return fail(RBM_ERR_INVALID, "rounds %d not in 1..%d", rounds, RBM_RBMR_MAX_ROUNDS);

@@ -18,17 +18,21 @@
 //   k_rbmr_round  round L: an iteration whose tag is still on all its
 //                 members runs; the others mark their members with the next
 //                 round's tag in the other tag word and queue themselves
-//   k_rbmr_tail   one workgroup runs whatever is pending after the last
-//                 round, in iteration order (usually nothing: the depth of
-//                 a window of N/p random pairs is about 12)
+//   k_rbmr_finish one workgroup continues the rounds for what is pending
+//                 after the last multi-workgroup round (a window of N/2
+//                 random pairs has depth 11 to 13, and after 8 rounds about
+//                 0.03 % of its iterations are left), then runs anything
+//                 still pending in iteration order
 // Batches are drawn again from the counter wherever they are needed (a few
 // ALU operations instead of a stored table read at random).  Tag of
 // iteration e (its offset in the window, < 2^22) in round g: ((1023 - g)
-// << 22) | e, g = 1 .. 1022 over a stretch of windows (the records are
-// refilled when g would pass 1022).  A later round's tags are below every
-// stale one, so the tags need no reset between rounds, and within a round
-// the earliest iteration wins.  Round L reads tag word L mod 2 and writes
-// the other, so what it reads was settled before it started.
+// << 22) | e, g = 1 .. 1022 over a stretch of windows (each window reserves
+// the round numbers of its multi-workgroup rounds and of the finishing
+// workgroup's budget; the records are retagged when g would pass 1022).  A
+// later round's tags are below every stale one, so the tags need no reset
+// between rounds, and within a round the earliest iteration wins.  Round L
+// reads tag word L mod 2 and writes the other, so what it reads was settled
+// before it started.
 #include <hip/hip_runtime.h>
 
 #include "rbm_rbmr.hpp"
@@ -37,6 +41,8 @@ namespace rbm {
 namespace {
 
 constexpr int TPB = 256;
+constexpr int FIN_TPB = 1024;
+constexpr uint32_t FIN_BUDGET = 64;  // single-workgroup rounds before the ordered rest
 enum : uint32_t { STREAM_RBMR_DRAW = 2u, STREAM_RBMR_NOISE = 3u };
 
 __device__ __forceinline__ uint32_t tag_of(uint32_t g, uint32_t e)
@@ -263,27 +269,79 @@ __global__ __launch_bounds__(TPB) void k_rbmr_round(RbmrArgs a, uint32_t L, uint
     }
 }
 
-// The iterations still pending after the last round, in iteration order, by
-// one thread (the workgroup finds the next one).
+// The iterations still pending after the last multi-workgroup round: one
+// workgroup continues the rounds on its own for at most `budget` rounds,
+// then runs whatever is left in iteration order on one thread.  Between its
+// rounds a device-scope release and acquire around the barrier make every
+// tag update (an atomic min carried out past the caches) and every position
+// of a round visible before the next reads them; the tags are read with
+// device-scope atomic loads.  Every round runs at least the earliest pending
+// iteration, so the rounds make progress.
 template <int D, int KERN, bool SPLIT>
-__global__ __launch_bounds__(TPB) void k_rbmr_tail(RbmrArgs a, uint32_t rounds, uint64_t kbase, RRec<D> *rec,
-                                                   const uint32_t *__restrict__ list, const uint32_t *__restrict__ counts)
+__global__ __launch_bounds__(FIN_TPB) void k_rbmr_finish(RbmrArgs a, uint32_t rounds, uint32_t g, uint32_t budget,
+                                                         uint64_t kbase, RRec<D> *rec, uint32_t *list0,
+                                                         uint32_t *list1, const uint32_t *__restrict__ counts)
 {
-    const uint32_t n = counts[rounds];
+    __shared__ uint32_t s_cnt;
+    __shared__ uint32_t red[FIN_TPB];
+    uint32_t *lists[2] = {list0, list1};
+    uint32_t n = counts[rounds];
+    uint32_t L = rounds;
+    for (uint32_t it = 0; n > 0 && it < budget; ++it, ++L) {
+        const uint32_t *lin = lists[L & 1u];
+        uint32_t *lout = lists[(L + 1u) & 1u];
+        const uint32_t wi = L & 1u, wo = wi ^ 1u;
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        for (uint32_t idx = threadIdx.x; idx < n; idx += FIN_TPB) {
+            const uint32_t e = lin[idx];
+            uint32_t m[RBMR_MAX_P];
+            draw_members(a, kbase + e, m);
+            const uint32_t t = tag_of(g + L, e);
+            // the positions are loaded with the tags (they are used only if
+            // the iteration is ready, and then nothing else writes them)
+            float xs[RBMR_MAX_P][D];
+            load_positions<D>(a, rec, m, xs);
+            bool ready = true;
+#pragma unroll
+            for (int r = 0; r < RBMR_MAX_P; ++r)
+                if (r < (int)a.p)
+                    ready = ready && __hip_atomic_load(&rec[m[r]].tag[wi], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) == t;
+            if (ready) {
+                run_iteration<D, KERN, SPLIT>(a, kbase + e, m, xs, rec);
+            } else {
+                const uint32_t t1 = tag_of(g + L + 1u, e);
+#pragma unroll
+                for (int r = 0; r < RBMR_MAX_P; ++r)
+                    if (r < (int)a.p) atomicMin(&rec[m[r]].tag[wo], t1);
+                lout[atomicAdd(&s_cnt, 1u)] = e;
+            }
+        }
+        // this round's tag updates and positions are complete before the
+        // next round reads them (the finishing workgroup runs alone, so the
+        // device-scope fences have little to write back)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        n = s_cnt;
+        __syncthreads();
+    }
     if (n == 0) return;
-    __shared__ uint32_t red[TPB];
+    // the rest in iteration order (the workgroup finds the next one)
+    const uint32_t *list = lists[L & 1u];
     uint32_t last = 0;
     bool first_pass = true;
     for (uint32_t it = 0; it < n; ++it) {
         uint32_t best = 0xffffffffu;
-        for (uint32_t i = threadIdx.x; i < n; i += TPB) {
+        for (uint32_t i = threadIdx.x; i < n; i += FIN_TPB) {
             const uint32_t e = list[i];
             if ((first_pass || e > last) && e < best) best = e;
         }
         red[threadIdx.x] = best;
         __syncthreads();
-        for (int s = TPB / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + s]);
+        for (int s2 = FIN_TPB / 2; s2 > 0; s2 >>= 1) {
+            if ((int)threadIdx.x < s2) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + s2]);
             __syncthreads();
         }
         const uint32_t e = red[0];
@@ -315,7 +373,7 @@ hipError_t launch_dk(const RbmrArgs &a, const RbmrLayout &lay, void *ws, float *
     uint32_t g = 1;
     for (uint64_t done = 0; done < niter;) {
         const uint32_t wcur = (uint32_t)((niter - done) < lay.window ? (niter - done) : lay.window);
-        if (g + R + 1u > 1022u) {
+        if (g + R + FIN_BUDGET + 1u > 1022u) {
             hipLaunchKernelGGL(k_rbmr_retag<D>, gn, dim3(TPB), 0, st, a.n, rec);
             g = 1;
         }
@@ -327,9 +385,9 @@ hipError_t launch_dk(const RbmrArgs &a, const RbmrLayout &lay, void *ws, float *
             hipLaunchKernelGGL((k_rbmr_round<D, KERN, SPLIT>), dim3(grid), dim3(TPB), 0, st, a, L, g + L, kbase + done,
                                wcur, rec, lists[L & 1u], lists[(L + 1u) & 1u], counts);
         }
-        hipLaunchKernelGGL((k_rbmr_tail<D, KERN, SPLIT>), dim3(1), dim3(TPB), 0, st, a, R, kbase + done, rec,
-                           lists[R & 1u], counts);
-        g += R + 1u;
+        hipLaunchKernelGGL((k_rbmr_finish<D, KERN, SPLIT>), dim3(1), dim3(FIN_TPB), 0, st, a, R, g, FIN_BUDGET,
+                           kbase + done, rec, lists[0], lists[1], counts);
+        g += R + FIN_BUDGET + 1u;
         done += wcur;
     }
     hipLaunchKernelGGL(k_rbmr_unpack<D>, gn, dim3(TPB), 0, st, a.n, rec, x);

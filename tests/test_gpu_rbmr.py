@@ -101,6 +101,21 @@ def test_rbmr_schedule_does_not_change_the_bits():
     assert np.array_equal(x.cpu().numpy(), ref)
 
 
+def test_rbmr_deep_windows_finish_in_order():
+    """N = 8 particles, windows of 1000 pairs: the dependency chains are
+    hundreds of iterations deep, so after one round across the GPU the
+    finishing workgroup's 64 rounds leave most of each window to its ordered
+    part.  Same bits as windows of 4 with 16 rounds, and the oracle's
+    sequential run."""
+    w = rbm_inputs.params_of("gauss2d-n1024-p2", n=8, p=2)
+    x0 = rbm_inputs.workload("gauss2d", 8, 3)
+    niter = 3000
+    deep = gpu_run(w, x0, 7, niter, window=1000, rounds=1)
+    shallow = gpu_run(w, x0, 7, niter, window=4, rounds=16)
+    assert np.array_equal(deep, shallow)
+    assert ora.rel_max_error(deep, ora.rbmr_run(op(w), 2, 7, niter, x0.astype(np.float64))) <= 1e-4
+
+
 def test_rbmr_rejects_bad_arguments():
     w = rbm_inputs.params_of("gauss2d-n1024-p2")
     x = torch.zeros((1024, 2), dtype=torch.float32, device="cuda")
