@@ -154,9 +154,9 @@ rbm_status rbm_forces(rbm_ctx *ctx, int64_t step, float *d_f, void *stream);
 rbm_status rbm_step_index(const rbm_ctx *ctx, int64_t *m);
 
 /* Wait for the stream and report device-side checks (a bucket larger than
- * the on-chip capacity, which has probability far below 1e-30 per step for
- * the supported sizes; a slot id >= N given to rbm_init): RBM_OK or
- * RBM_ERR_DEVICE. */
+ * the on-chip capacity, which by a Chernoff bound on the bucket counts has
+ * probability below 1e-15 per step for every supported N; a slot id >= N
+ * given to rbm_init): RBM_OK or RBM_ERR_DEVICE. */
 rbm_status rbm_check(rbm_ctx *ctx, void *stream);
 
 /* Kernels of one step, for rbm_phase_times (a kernel a step does not need
