@@ -120,10 +120,17 @@ __device__ __forceinline__ uint32_t wave0_exclusive_scan(const uint32_t *a, uint
 // ---------------------------------------------------------------------------
 constexpr uint32_t TILE = RBM_TILE;    // slots per coarse-scatter workgroup
 constexpr uint32_t CHUNK = RBM_CHUNK;  // records per split workgroup
-constexpr int LVL_TPB = RBM_LVL_TPB;
-constexpr int LVL_P = RBM_LVL_P;       // records per thread
-constexpr int LVL_RPT = RBM_LVL_RPT;   // records per thread and LDS round
-static_assert(LVL_P % 4 == 0 && LVL_P % LVL_RPT == 0, "staging rounds must divide the records per thread");
+// A staging level: TPB threads holding P records each, LDS rounds of RPT
+// records per thread.
+template <int TPB_, int P_, int RPT_>
+struct Lvl {
+    static constexpr int TPB = TPB_, P = P_, RPT = RPT_;
+    static_assert(P % 4 == 0 && P % RPT == 0, "staging rounds must divide the records per thread");
+};
+using LvlScatter = Lvl<RBM_SCATTER_TPB, RBM_SCATTER_P, RBM_LVL_RPT>;
+using LvlSplit = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_P, RBM_LVL_RPT>;
+constexpr int SCATTER_TPB = LvlScatter::TPB;
+constexpr int SPLIT_TPB = LvlSplit::TPB;
 constexpr int LVL_NB = 256;            // largest digit count of a level
 
 __global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, uint32_t *cnt)
@@ -239,48 +246,48 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
 }
 
 // ---------------------------------------------------------------------------
-// staged writes: a workgroup's LVL_P x LVL_TPB = 8K records (in registers) go
+// staged writes: a workgroup's C::P x C::TPB = 8K records (in registers) go
 // to per-digit runs.  Each digit's run is reserved once with one global
 // atomic on the digit's cursor; the records are then ordered by digit in LDS,
-// LVL_RPT x LVL_TPB at a time, so that consecutive lanes store to consecutive
+// C::RPT x C::TPB at a time, so that consecutive lanes store to consecutive
 // addresses.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, class C>
 struct StageLds {
-    Rec<D> rec[LVL_RPT * LVL_TPB];
-    uint32_t w[LVL_RPT * LVL_TPB];
-    uint16_t dig[LVL_RPT * LVL_TPB];
+    Rec<D> rec[C::RPT * C::TPB];
+    uint32_t w[C::RPT * C::TPB];
+    uint16_t dig[C::RPT * C::TPB];
     uint32_t cnt[LVL_NB];   // round counts / tile counts
     uint32_t start[LVL_NB]; // round starts
     uint32_t gbase[LVL_NB]; // next global position of each digit
 };
 
 // digit(w) = (fine_of(w) >> shift) & mask
-template <int D>
-__device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const uint32_t (&rid)[LVL_P],
-                             const uint32_t (&w)[LVL_P], uint32_t nact, uint32_t nbuck,
+template <int D, class C>
+__device__ void staged_write(StageLds<D, C> &L, const float (&rx)[C::P][D], const uint32_t (&rid)[C::P],
+                             const uint32_t (&w)[C::P], uint32_t nact, uint32_t nbuck,
                              uint32_t shift, uint32_t mask, uint32_t ndig, uint32_t *gcur,
                              Rec<D> *__restrict__ out, uint32_t *__restrict__ wout)
 {
     const uint32_t tid = threadIdx.x;
     // record k of this thread is active if k < nact (the caller orders them so)
-    for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.cnt[d] = 0;
+    for (uint32_t d = tid; d < ndig; d += C::TPB) L.cnt[d] = 0;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < LVL_P; ++k)
+    for (int k = 0; k < C::P; ++k)
         if ((uint32_t)k < nact) atomicAdd(&L.cnt[(fine_of(w[k], nbuck) >> shift) & mask], 1u);
     __syncthreads();
-    for (uint32_t d = tid; d < ndig; d += LVL_TPB)
+    for (uint32_t d = tid; d < ndig; d += C::TPB)
         L.gbase[d] = L.cnt[d] ? atomicAdd(&gcur[d], L.cnt[d]) : 0u;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < LVL_P / LVL_RPT; ++r) {
-        for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.cnt[d] = 0;
+    for (int r = 0; r < C::P / C::RPT; ++r) {
+        for (uint32_t d = tid; d < ndig; d += C::TPB) L.cnt[d] = 0;
         __syncthreads();
-        uint32_t lr[LVL_RPT];
+        uint32_t lr[C::RPT];
 #pragma unroll
-        for (int q = 0; q < LVL_RPT; ++q) {
-            const int k = LVL_RPT * r + q;
+        for (int q = 0; q < C::RPT; ++q) {
+            const int k = C::RPT * r + q;
             lr[q] = (uint32_t)k < nact ? atomicAdd(&L.cnt[(fine_of(w[k], nbuck) >> shift) & mask], 1u) : 0u;
         }
         __syncthreads();
@@ -288,8 +295,8 @@ __device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const 
         if (tid < 64) total = wave0_exclusive_scan(L.cnt, L.start, ndig);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < LVL_RPT; ++q) {
-            const int k = LVL_RPT * r + q;
+        for (int q = 0; q < C::RPT; ++q) {
+            const int k = C::RPT * r + q;
             if ((uint32_t)k < nact) {
                 const uint32_t d = (fine_of(w[k], nbuck) >> shift) & mask;
                 const uint32_t slot = L.start[d] + lr[q];
@@ -305,38 +312,38 @@ __device__ void staged_write(StageLds<D> &L, const float (&rx)[LVL_P][D], const 
         __syncthreads();
         const uint32_t rt = L.start[ndig - 1] + L.cnt[ndig - 1];
         (void)total;
-        for (uint32_t i = tid; i < rt; i += LVL_TPB) {
+        for (uint32_t i = tid; i < rt; i += C::TPB) {
             const uint32_t d = L.dig[i];
             const uint32_t g = L.gbase[d] + (i - L.start[d]);
             out[g] = L.rec[i];
             wout[g] = L.w[i];
         }
         __syncthreads();
-        for (uint32_t d = tid; d < ndig; d += LVL_TPB) L.gbase[d] += L.cnt[d];
+        for (uint32_t d = tid; d < ndig; d += C::TPB) L.gbase[d] += L.cnt[d];
         __syncthreads();
     }
 }
 
-// Coarse scatter: tile of LVL_P x LVL_TPB slots.  Thread t holds slots
-// 4(t + LVL_TPB g) + j.
+// Coarse scatter: tile of P x TPB slots.  Thread t holds slots
+// 4(t + TPB g) + j.
 // Records of a partial last tile are packed so that the first nact of each
 // thread are the valid ones.
 template <int D>
-__global__ __launch_bounds__(LVL_TPB) void k_scatter_coarse(StepArgs s, uint32_t shift, uint32_t nb1,
+__global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint32_t shift, uint32_t nb1,
                                                             const Rec<D> *__restrict__ state,
                                                             uint32_t *__restrict__ ccur,
                                                             Rec<D> *__restrict__ stage,
                                                             uint32_t *__restrict__ wout)
 {
-    __shared__ StageLds<D> L;
+    __shared__ StageLds<D, LvlScatter> L;
     const uint32_t base = blockIdx.x * TILE;
     const uint32_t end = min(base + TILE, s.n);
-    float rx[LVL_P][D];
-    uint32_t rid[LVL_P], w[LVL_P];
+    float rx[LvlScatter::P][D];
+    uint32_t rid[LvlScatter::P], w[LvlScatter::P];
     uint32_t nact = 0;
 #pragma unroll
-    for (int g = 0; g < LVL_P / 4; ++g) {
-        const uint32_t k = base + 4 * (threadIdx.x + g * LVL_TPB);
+    for (int g = 0; g < LvlScatter::P / 4; ++g) {
+        const uint32_t k = base + 4 * (threadIdx.x + g * LvlScatter::TPB);
         const uint4 w4 = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -354,13 +361,13 @@ __global__ __launch_bounds__(LVL_TPB) void k_scatter_coarse(StepArgs s, uint32_t
         // records are a prefix
         nact += (k < end) ? min(4u, end - k) : 0u;
     }
-    staged_write<D>(L, rx, rid, w, nact, s.nbuck, shift, 0xffffffffu, nb1, ccur, stage, wout);
+    staged_write<D, LvlScatter>(L, rx, rid, w, nact, s.nbuck, shift, 0xffffffffu, nb1, ccur, stage, wout);
 }
 
 // Split: chunk j of coarse bucket c (workgroup c * jmax + j) into the 2^shift
 // fine buckets of c.
 template <int D>
-__global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
+__global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
                                                    const uint32_t *__restrict__ cstart,
                                                    const Rec<D> *__restrict__ in,
                                                    const uint32_t *__restrict__ win,
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, u
                                                    uint32_t *__restrict__ wout,
                                                    uint32_t *__restrict__ flags)
 {
-    __shared__ StageLds<D> L;
+    __shared__ StageLds<D, LvlSplit> L;
     const uint32_t c = blockIdx.x / jmax, j = blockIdx.x % jmax;
     const uint32_t c0 = cstart[c], c1 = cstart[c + 1];
     // the jmax chunks must cover the coarse bucket (mean + 16 sd of room)
@@ -377,13 +384,13 @@ __global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, u
     const uint32_t lo = min(c0 + j * CHUNK, c1);
     const uint32_t hi = min(lo + CHUNK, c1);
     if (lo == hi) return;
-    float rx[LVL_P][D];
-    uint32_t rid[LVL_P], w[LVL_P];
-    // thread t holds records lo + t + LVL_TPB k: the valid ones are a prefix in k
+    float rx[LvlSplit::P][D];
+    uint32_t rid[LvlSplit::P], w[LvlSplit::P];
+    // thread t holds records lo + t + LvlSplit::TPB k: the valid ones are a prefix in k
     uint32_t nact = 0;
 #pragma unroll
-    for (int k = 0; k < LVL_P; ++k) {
-        const uint32_t e = lo + threadIdx.x + k * LVL_TPB;
+    for (int k = 0; k < LvlSplit::P; ++k) {
+        const uint32_t e = lo + threadIdx.x + k * LvlSplit::TPB;
         Rec<D> t{};
         w[k] = 0u;
         if (e < hi) {
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(LVL_TPB) void k_split(StepArgs s, uint32_t shift, u
         rid[k] = t.id;
     }
     const uint32_t ndig = 1u << shift;
-    staged_write<D>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
+    staged_write<D, LvlSplit>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,15 +988,15 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         if (pl.shift > 0) {
             auto *stage2 = at<Rec<2>>(ws, pl.off_stage2);
             auto *w2 = at<uint32_t>(ws, pl.off_w2);
-            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s,
+            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s,
                                pl.shift, pl.nb1, state, ccur, stage1, w1);
             mark(ev, 4, st);
-            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(LVL_TPB), 0, st, s,
+            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s,
                                pl.shift, pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
             src = stage2;
             wsrc = w2;
         } else {
-            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, 0u,
+            hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s, 0u,
                                pl.nbuck, state, fcur, stage1, w1);
             mark(ev, 4, st);
         }
@@ -1069,17 +1076,17 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     if (split) {
         auto *stage2 = at<Rec<D>>(ws, pl.off_stage2);
         auto *w2 = at<uint32_t>(ws, pl.off_w2);
-        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, pl.shift,
+        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s, pl.shift,
                            pl.nb1, state, ccur, stage1, w1);
         mark(ev, 4, st);
-        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(LVL_TPB), 0, st, s, pl.shift,
+        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
                            pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
         mark(ev, 5, st);
         src = stage2;
         wsrc = w2;
     } else {
         // one level: the coarse buckets are the fine buckets
-        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(LVL_TPB), 0, st, s, 0u,
+        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s, 0u,
                            pl.nbuck, state, fcur, stage1, w1);
         mark(ev, 4, st);
         mark(ev, 5, st);
