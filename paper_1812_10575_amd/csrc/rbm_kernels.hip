@@ -16,7 +16,7 @@
 //                    coarse buckets; each (tile, bucket) run is reserved with
 //                    one atomic and written through an LDS reorder so that
 //                    lanes store to consecutive addresses
-//   k_split          each 8K-record chunk of a coarse bucket goes to its
+//   k_split          each 12K-record chunk of a coarse bucket goes to its
 //                    fine buckets the same way
 //   k_sort_step      one workgroup per fine bucket: order it in LDS by the
 //                    unique key, evaluate the batch forces of eq. (2.3) for
@@ -128,7 +128,7 @@ struct Lvl {
     static_assert(P % 4 == 0 && P % RPT == 0, "staging rounds must divide the records per thread");
 };
 using LvlScatter = Lvl<RBM_SCATTER_TPB, RBM_SCATTER_P, RBM_LVL_RPT>;
-using LvlSplit = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_P, RBM_LVL_RPT>;
+using LvlSplit = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_P, RBM_SPLIT_RPT>;
 constexpr int SCATTER_TPB = LvlScatter::TPB;
 constexpr int SPLIT_TPB = LvlSplit::TPB;
 constexpr int LVL_NB = 256;            // largest digit count of a level
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
 }
 
 // ---------------------------------------------------------------------------
-// staged writes: a workgroup's C::P x C::TPB = 8K records (in registers) go
-// to per-digit runs.  Each digit's run is reserved once with one global
+// staged writes: a workgroup's C::P x C::TPB records (in registers) go to
+// per-digit runs.  Each digit's run is reserved once with one global
 // atomic on the digit's cursor; the records are then ordered by digit in LDS,
 // C::RPT x C::TPB at a time, so that consecutive lanes store to consecutive
 // addresses.

@@ -24,15 +24,17 @@
 #define RBM_KEY_SETS 8
 #define RBM_MAX_FINE 32768
 // Scatter and split workgroups: threads holding a fixed number of records
-// each, staged through LDS 4 per thread at a time.  The coarse scatter runs
-// 512 threads with 16 records (two workgroups per CU); the split 1024
-// threads with 8, so that each LDS round (4096 records) writes runs twice as
-// long (fewer partly written lines) with one workgroup per CU.
+// each, staged through LDS a few per thread at a time.  The coarse scatter
+// runs 512 threads with 16 records, 4 per round (two workgroups per CU); the
+// split 1024 threads with 12, 6 per round, so that each LDS round (6144
+// records) writes runs three times as long (fewer partly written lines) with
+// one workgroup per CU.
 #define RBM_SCATTER_TPB 512
 #define RBM_SCATTER_P 16
-#define RBM_SPLIT_TPB 1024
-#define RBM_SPLIT_P 8
 #define RBM_LVL_RPT 4
+#define RBM_SPLIT_TPB 1024
+#define RBM_SPLIT_P 12
+#define RBM_SPLIT_RPT 6
 #define RBM_TILE (RBM_SCATTER_P * RBM_SCATTER_TPB)
 #define RBM_CHUNK (RBM_SPLIT_P * RBM_SPLIT_TPB)
 #define RBM_SPLIT_SHIFT 7
