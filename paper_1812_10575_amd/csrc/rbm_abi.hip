@@ -141,7 +141,7 @@ Plan make_plan(const rbm_params *prm)
             const double mean = (double)pl.n / pl.nb1;
             pl.jmax = (uint32_t)std::ceil((mean + 16.0 * std::sqrt(mean) + 64.0) / RBM_CHUNK);
         }
-        pl.cap = (uint64_t)pl.n <= (uint64_t)pl.nbuck * RBM_BUCKET_MEAN ? RBM_SORT_CAP : RBM_SORT_CAP_BIG;
+        pl.cap = RBM_SORT_CAP;
         pl.ntiles = (pl.n + RBM_TILE - 1) / RBM_TILE;
         // about 128 key-count tiles, a multiple of 4 slots each
         uint32_t tf = (pl.n + 127) / 128;
@@ -172,6 +172,18 @@ Plan make_plan(const rbm_params *prm)
         pl.off_fcur = take((size_t)pl.kb * pl.nbuck * 4);
         pl.off_cstart = take((size_t)pl.kb * (pl.nb1 + 1) * 4);
         pl.off_ccur = take((size_t)pl.kb * pl.nb1 * 4);
+        // fused steps need the split level; the control-variate step keeps
+        // its own order of kernels
+        const char *env = getenv("RBM_FUSE");
+        pl.fuse = pl.shift > 0 && !prm->cv && !(env && env[0] == '0');
+        if (pl.fuse) {
+            pl.ntx = (pl.nbuck + RBM_CROSS_G - 1) / RBM_CROSS_G;
+            pl.off_xrow = take((size_t)pl.kb * pl.nbuck * pl.nb1 * 2);
+            pl.off_xtsum = take((size_t)pl.kb * pl.ntx * pl.nb1 * 4);
+            pl.off_xbase = take((size_t)pl.kb * pl.ntx * pl.nb1 * 4);
+            pl.off_fixpos = take((size_t)pl.n * 4);
+            pl.off_xdig = take((size_t)pl.kb * align256(pl.n));
+        }
     }
     pl.cv = prm->cv;
     if (pl.cv) {
@@ -358,7 +370,12 @@ rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
             // this step's share of the key passes was timed with the group's first step
             for (int i = 0; i < 4; ++i) (void)hipEventRecord(ev[i], hs);
         }
-        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, ev, set, true);
+        // inside a group the sort of each step but the last writes the next
+        // step's coarse buckets; the group's last step leaves the state in
+        // slot order
+        uint32_t fuse = 0;
+        if (pl.fuse) fuse = (set > 0 ? 1u : 0u) | (set + 1 < group ? 2u : 0u);
+        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, ev, set, true, fuse);
         if (e != hipSuccess) return hip_fail(e, "rbm_step launch");
         ++set;
         ctx->m += 1;

@@ -4,7 +4,7 @@
 // One step m, with the particles held as records (x, id) in "slot" order
 // (the order left by the previous step).  Slot k draws the PERM word w_k; the
 // key (w_k << 32 | id) orders the particles.  The word range is cut into B
-// equal "fine buckets", f = floor(w B / 2^32) (about 960 records each),
+// equal "fine buckets", f = floor(w B / 2^32) (about 1920 records each),
 // grouped 2^shift at a time into coarse buckets.
 //
 //   k_key_count      per tile of slots, fine-bucket histogram of the words
@@ -24,6 +24,13 @@
 //                    update, write each record at its sorted rank (its slot
 //                    for step m+1)
 //   k_fixup          the batches cut by a fine-bucket boundary
+//
+// Fused steps: the key passes of a group of steps run ahead of them, and the
+// rank of a record after step m is its slot at step m+1, so the sort kernel
+// knows every record's coarse bucket of the next step.  Inside a group it
+// writes the updated records straight into those coarse buckets (k_cross_count
+// and k_cross_scan give each bucket its write offsets), and the next step
+// starts with the split: one pass over the records fewer per step.
 //
 // Records land in a run in whatever order the atomics give; the in-LDS sort
 // by the unique key makes the result independent of it.  Up to 128 fine
@@ -133,22 +140,38 @@ constexpr int SCATTER_TPB = LvlScatter::TPB;
 constexpr int SPLIT_TPB = LvlSplit::TPB;
 constexpr int LVL_NB = 256;            // largest digit count of a level
 
-__global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, uint32_t *cnt)
+// dig != nullptr (fused steps): also the coarse digit of every slot, one
+// byte each, key set y at dig + y * dstride.
+__global__ __launch_bounds__(1024) void k_key_count(StepArgs s, uint32_t tilef, uint32_t *cnt, uint32_t shift,
+                                                    uint8_t *dig, size_t dstride)
 {
     extern __shared__ uint32_t hist[];
     const uint32_t nb = s.nbuck;
     s.m += blockIdx.y;  // key set y holds step m + y
     cnt += (size_t)blockIdx.y * gridDim.x * nb;
+    if (dig) dig += (size_t)blockIdx.y * dstride;
     for (uint32_t i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * tilef;
     const uint32_t end = min(base + tilef, s.n);
     for (uint32_t k = base + 4 * threadIdx.x; k < end; k += 4 * 1024) {
         const uint4 w = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
-        atomicAdd(&hist[fine_of(w.x, nb)], 1u);
-        if (k + 1 < end) atomicAdd(&hist[fine_of(w.y, nb)], 1u);
-        if (k + 2 < end) atomicAdd(&hist[fine_of(w.z, nb)], 1u);
-        if (k + 3 < end) atomicAdd(&hist[fine_of(w.w, nb)], 1u);
+        const uint32_t f0 = fine_of(w.x, nb), f1 = fine_of(w.y, nb), f2 = fine_of(w.z, nb), f3 = fine_of(w.w, nb);
+        atomicAdd(&hist[f0], 1u);
+        if (k + 1 < end) atomicAdd(&hist[f1], 1u);
+        if (k + 2 < end) atomicAdd(&hist[f2], 1u);
+        if (k + 3 < end) atomicAdd(&hist[f3], 1u);
+        if (dig) {
+            if (k + 3 < end) {
+                *reinterpret_cast<uchar4 *>(dig + k) =
+                    make_uchar4((uint8_t)(f0 >> shift), (uint8_t)(f1 >> shift), (uint8_t)(f2 >> shift),
+                                (uint8_t)(f3 >> shift));
+            } else {
+                dig[k] = (uint8_t)(f0 >> shift);
+                if (k + 1 < end) dig[k + 1] = (uint8_t)(f1 >> shift);
+                if (k + 2 < end) dig[k + 2] = (uint8_t)(f2 >> shift);
+            }
+        }
     }
     __syncthreads();
     uint32_t *row = cnt + (size_t)blockIdx.x * nb;
@@ -243,6 +266,80 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
         cstart[nb1] = n;
     }
     if (over) atomicOr(flags, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// cross counts of a fused transition (key set t -> t + 1, t = blockIdx.y):
+// the records of step m + t at ranks [fstart_t[f], fstart_t[f + 1]) are the
+// slots of fine bucket f; the sort kernel of that bucket writes each of them
+// into its coarse bucket of step m + t + 1, the digit that the key count
+// stored for that slot.  Per tile of RBM_CROSS_G fine buckets: xrow[f][c]
+// (records of bucket f headed for coarse bucket c) and the tile's column sums
+// xtsum[x][c].
+// ---------------------------------------------------------------------------
+constexpr uint32_t XG = RBM_CROSS_G;
+
+__global__ __launch_bounds__(256) void k_cross_count(uint32_t nbuck, uint32_t nb1, uint32_t ntx, size_t dstride,
+                                                     const uint32_t *__restrict__ fstart,
+                                                     const uint8_t *__restrict__ dig,
+                                                     uint16_t *__restrict__ xrow,
+                                                     uint32_t *__restrict__ xtsum)
+{
+    __shared__ uint32_t hist[XG * 256];
+    __shared__ uint32_t bnd[XG + 1];
+    const uint32_t t = blockIdx.y, x = blockIdx.x, tid = threadIdx.x;
+    fstart += (size_t)t * (nbuck + 1);
+    dig += (size_t)(t + 1) * dstride;  // the coarse digits of step m + t + 1
+    xrow += (size_t)t * nbuck * nb1;
+    xtsum += (size_t)t * ntx * nb1;
+    const uint32_t f0 = x * XG;
+    const uint32_t ng = min(XG, nbuck - f0);
+    for (uint32_t i = tid; i < XG * nb1; i += 256) hist[i] = 0;
+    if (tid <= ng) bnd[tid] = fstart[f0 + tid];
+    __syncthreads();
+    for (uint32_t g = 0; g < ng; ++g) {
+        const uint32_t b1 = bnd[g + 1];
+        uint32_t *h = hist + g * nb1;
+        uint32_t k = bnd[g] + tid;
+        for (; k + 768 < b1; k += 1024) {
+            const uint32_t c0 = dig[k], c1 = dig[k + 256], c2 = dig[k + 512], c3 = dig[k + 768];
+            atomicAdd(&h[c0], 1u);
+            atomicAdd(&h[c1], 1u);
+            atomicAdd(&h[c2], 1u);
+            atomicAdd(&h[c3], 1u);
+        }
+        for (; k < b1; k += 256) atomicAdd(&h[dig[k]], 1u);
+    }
+    __syncthreads();
+    uint16_t *row = xrow + (size_t)f0 * nb1;
+    for (uint32_t i = tid; i < ng * nb1; i += 256) row[i] = (uint16_t)min(hist[i], 65535u);
+    for (uint32_t c = tid; c < nb1; c += 256) {
+        uint32_t sum = 0;
+        for (uint32_t g = 0; g < ng; ++g) sum += hist[g * nb1 + c];
+        xtsum[(size_t)x * nb1 + c] = sum;
+    }
+}
+
+// Coarse write offsets of a fused transition: xbase[x][c] = cstart_{t+1}[c]
+// + the records of tiles 0 .. x - 1 headed for coarse bucket c.  One
+// workgroup per (c, t).
+__global__ __launch_bounds__(256) void k_cross_scan(uint32_t nb1, uint32_t ntx,
+                                                    const uint32_t *__restrict__ xtsum,
+                                                    const uint32_t *__restrict__ cstart,
+                                                    uint32_t *__restrict__ xbase)
+{
+    constexpr int PER = RBM_MAX_FINE / RBM_CROSS_G / 256;
+    __shared__ uint32_t a[256 * PER];
+    __shared__ uint32_t tmp[4];
+    const uint32_t c = blockIdx.x, t = blockIdx.y;
+    xtsum += (size_t)t * ntx * nb1;
+    xbase += (size_t)t * ntx * nb1;
+    cstart += (size_t)(t + 1) * (nb1 + 1);
+    for (uint32_t i = threadIdx.x; i < 256u * PER; i += 256) a[i] = i < ntx ? xtsum[(size_t)i * nb1 + c] : 0u;
+    __syncthreads();
+    block_exclusive_scan<256, PER>(a, tmp);
+    const uint32_t c0 = cstart[c];
+    for (uint32_t i = threadIdx.x; i < ntx; i += 256) xbase[(size_t)i * nb1 + c] = c0 + a[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -365,7 +462,7 @@ __global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint
 }
 
 // Split: chunk j of coarse bucket c (workgroup c * jmax + j) into the 2^shift
-// fine buckets of c.
+// fine buckets of c, adding the pending noise of s.
 template <int D>
 __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
                                                    const uint32_t *__restrict__ cstart,
@@ -395,6 +492,9 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
         w[k] = 0u;
         if (e < hi) {
             t = in[e];
+            // records written by a fused sort still lack the previous step's
+            // noise (the host clears s.pssd when the coarse scatter added it)
+            add_pending_noise<D>(s, t.x, t.id);
             w[k] = win[e];
             ++nact;
         }
@@ -409,25 +509,26 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
 // ---------------------------------------------------------------------------
 // per-bucket sort + batch force + Euler-Maruyama
 // ---------------------------------------------------------------------------
-// Write-back of one particle: the force (by id) in force mode, else the
-// Euler-Maruyama update written at sorted rank r.
+// End of one particle's step: in force mode its force is written (by id)
+// and the record comes back unchanged; else the record with the
+// Euler-Maruyama update applied.
 template <int D>
-__device__ __forceinline__ void finish(const StepArgs &s, float (&x)[D], float (&f)[D], uint32_t id,
-                                       uint32_t r, Rec<D> *dst, float *__restrict__ fout)
+__device__ __forceinline__ Rec<D> finish(const StepArgs &s, float (&x)[D], float (&f)[D], uint32_t id,
+                                         float *__restrict__ fout)
 {
     if (fout) {
         if (id < s.n) {  // ids are < N unless a flagged overflow left stale data
 #pragma unroll
             for (int c = 0; c < D; ++c) fout[(size_t)id * D + c] = f[c];
         }
-        return;
+    } else {
+        drift_update<D>(s, x, f);
     }
-    drift_update<D>(s, x, f);
     Rec<D> o;
 #pragma unroll
     for (int c = 0; c < D; ++c) o.x[c] = x[c];
     o.id = id;
-    dst[r] = o;
+    return o;
 }
 
 // LDS slot of the record at global rank r in a bucket starting at lo.
@@ -439,9 +540,8 @@ struct Slot {
 // Member r of the batch of ranks [bs, bs + sz) (any size): its force by
 // direct summation.
 template <int D, int KERN>
-__device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *srec, Slot pad,
-                                               uint32_t bs, uint32_t sz, uint32_t r, Rec<D> *dst,
-                                               float *__restrict__ fout)
+__device__ __forceinline__ Rec<D> member_generic(const StepArgs &s, const Rec<D> *srec, Slot pad,
+                                                 uint32_t bs, uint32_t sz, uint32_t r, float *__restrict__ fout)
 {
     const Rec<D> me = srec[pad(r)];
     float xi[D], f[D];
@@ -455,7 +555,7 @@ __device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *
     const float inv = (sz == s.p) ? s.inv_p1 : s.inv_last;
 #pragma unroll
     for (int c = 0; c < D; ++c) f[c] *= inv;
-    finish<D>(s, xi, f, me.id, r, dst, fout);
+    return finish<D>(s, xi, f, me.id, fout);
 }
 
 // Member r of a batch of exactly PM members starting at rank bs: its force
@@ -464,8 +564,8 @@ __device__ __forceinline__ void member_generic(const StepArgs &s, const Rec<D> *
 // d = 3, six workgroups per CU); a thread per batch evaluating each pair once
 // needed 98 and fitted four.  The sum over j is in the same order either way.
 template <int D, int KERN, int PM>
-__device__ __forceinline__ void member_fixed(const StepArgs &s, const Rec<D> *srec, Slot pad, uint32_t bs,
-                                             uint32_t r, Rec<D> *dst, float *__restrict__ fout)
+__device__ __forceinline__ Rec<D> member_fixed(const StepArgs &s, const Rec<D> *srec, Slot pad, uint32_t bs,
+                                               uint32_t r, float *__restrict__ fout)
 {
     const Rec<D> me = srec[pad(r)];
     float xi[D], f[D];
@@ -484,8 +584,7 @@ __device__ __forceinline__ void member_fixed(const StepArgs &s, const Rec<D> *sr
                 pair_flow<D>(s.dt, xi, xj, y);
             else
                 pair_flow_linear<D>(s.flowc, xi, xj, y);
-            finish<D>(s, y, f, me.id, r, dst, fout);
-            return;
+            return finish<D>(s, y, f, me.id, fout);
         }
     }
 #pragma unroll
@@ -495,8 +594,41 @@ __device__ __forceinline__ void member_fixed(const StepArgs &s, const Rec<D> *sr
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) f[c] *= s.inv_p1;
-    finish<D>(s, xi, f, me.id, r, dst, fout);
+    return finish<D>(s, xi, f, me.id, fout);
 }
+
+// The member at rank r (inside the bucket's whole batches): its batch from
+// the batch geometry, p == PM with a compile-time divisor when PM > 0.
+template <int D, int KERN, int PM>
+__device__ __forceinline__ Rec<D> batch_member(const StepArgs &s, const Rec<D> *srec, Slot pad, uint32_t r,
+                                               float *__restrict__ fout)
+{
+    if constexpr (PM > 0) {
+        uint32_t q = r / (uint32_t)PM;
+        if (q > s.nbat - 1) q = s.nbat - 1;
+        const uint32_t bs = q * (uint32_t)PM;
+        if (q != s.nbat - 1 || s.n - bs == (uint32_t)PM) return member_fixed<D, KERN, PM>(s, srec, pad, bs, r, fout);
+        return member_generic<D, KERN>(s, srec, pad, bs, s.n - bs, r, fout);
+    } else {
+        uint32_t bs, be;
+        batch_of(s, r, bs, be);
+        return member_generic<D, KERN>(s, srec, pad, bs, be - bs, r, fout);
+    }
+}
+
+// Output of a fused step's sort kernel: the coarse buckets of the next step
+// (records and their PERM words of that step), placed by the cross counts of
+// the transition.
+template <int D>
+struct FuseOut {
+    const uint16_t *xrow;    // [nbuck][nb1] records of fine bucket f headed for coarse bucket c
+    const uint32_t *xbase;   // [ntx][nb1] coarse write offset of each cross tile
+    uint32_t *fixpos;        // [n] position written for each record of a cut batch, by rank
+    Rec<D> *out;             // coarse buckets of the next step
+    uint32_t *wout;          // their PERM words
+    uint32_t nb1;
+    uint32_t shift;
+};
 
 // One workgroup per fine bucket [lo, hi) (SINGLE: the whole system, read
 // from the slot-ordered state, PERM words drawn here).
@@ -511,19 +643,29 @@ __device__ __forceinline__ void member_fixed(const StepArgs &s, const Rec<D> *sr
 //      unchanged for k_fixup.
 // fout != nullptr: forces only (by id); dst gets only the cut batches.
 // SORTONLY: every record is written to dst at its rank, nothing else.
-template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SBITS, bool SORTONLY = false, int PM = 0>
+// FUSED: the updated records go to the next step's coarse buckets (fo), not
+// to dst; the records of cut batches also go to dst at their ranks, and
+// their positions in fo.out to fo.fixpos, for k_fixup.
+template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SBITS, bool SORTONLY = false, int PM = 0,
+          bool FUSED = false>
 __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src,
                                                    const uint32_t *__restrict__ wsrc,
                                                    const uint32_t *__restrict__ bstart,
                                                    Rec<D> *dst, float *__restrict__ fout,
-                                                   uint32_t *__restrict__ flags)
+                                                   uint32_t *__restrict__ flags, FuseOut<D> fo)
 {
     constexpr int S = 1 << SBITS;
     constexpr int E = (CAP + TPB - 1) / TPB;
     static_assert(S % TPB == 0, "sub-bucket count must be a multiple of the block");
+    static_assert(!FUSED || (!SINGLE && !SORTONLY), "fused output is for the multi-bucket step");
     constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
     constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
     __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
+    // fused output: 2 KB of per-digit arrays, the Philox words of the
+    // bucket's ranks (WT: at most CAP + 6 of them, in blocks of 4), the
+    // staging rounds
+    constexpr size_t WT = 4 * ((CAP + 6) / 4 + 1);
+    static_assert(2048 + WT * 4 + 64 * (sizeof(Rec<D>) + 4) <= sizeof(lds), "fused staging does not fit");
     __shared__ uint32_t scan_tmp[TPB / 64];
     uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
     uint32_t *idv = wv + CAP;
@@ -547,6 +689,18 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         return;
     }
 
+    // fused: thread c < nb1 gathers the write offset of coarse bucket c for
+    // this bucket (its tile's base plus the earlier buckets of the tile) and
+    // this bucket's own count, to check against the counts made here
+    uint32_t fgo = 0, fchk = 0;
+    if constexpr (FUSED) {
+        if (tid < fo.nb1) {
+            const uint32_t f = blockIdx.x, f0 = f - f % XG;
+            fgo = fo.xbase[(size_t)(f / XG) * fo.nb1 + tid];
+            for (uint32_t g = f0; g < f; ++g) fgo += fo.xrow[(size_t)g * fo.nb1 + tid];
+            fchk = fo.xrow[(size_t)f * fo.nb1 + tid];
+        }
+    }
     for (uint32_t i = tid; i <= (uint32_t)S; i += TPB) cnt[i] = 0;
     __syncthreads();
 
@@ -638,25 +792,102 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     const bool any = q_first <= (int64_t)s.nbat - 1 && q_last >= q_first;
     const uint32_t ins_lo = any ? (uint32_t)q_first * p : hi;
     const uint32_t ins_hi = any ? (q_last == (int64_t)s.nbat - 1 ? s.n : (uint32_t)(q_last + 1) * p) : hi;
-    for (uint32_t l = tid; l < nb; l += TPB) {
-        const uint32_t r = lo + l;
-        if (r < ins_lo || r >= ins_hi) dst[r] = srec[pad(r)];
-    }
-    if (!any) return;
-    for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
-        if constexpr (PM > 0) {
-            // p == PM: batch geometry with a compile-time divisor
-            uint32_t q = r / (uint32_t)PM;
-            if (q > s.nbat - 1) q = s.nbat - 1;
-            const uint32_t bs = q * (uint32_t)PM;
-            if (q != s.nbat - 1 || s.n - bs == (uint32_t)PM)
-                member_fixed<D, KERN, PM>(s, srec, pad, bs, r, dst, fout);
-            else
-                member_generic<D, KERN>(s, srec, pad, bs, s.n - bs, r, dst, fout);
-        } else {
-            uint32_t bs, be;
-            batch_of(s, r, bs, be);
-            member_generic<D, KERN>(s, srec, pad, bs, be - bs, r, dst, fout);
+    if constexpr (!FUSED) {
+        for (uint32_t l = tid; l < nb; l += TPB) {
+            const uint32_t r = lo + l;
+            if (r < ins_lo || r >= ins_hi) dst[r] = srec[pad(r)];
+        }
+        if (!any) return;
+        for (uint32_t r = ins_lo + tid; r < ins_hi; r += TPB) {
+            const Rec<D> o = batch_member<D, KERN, PM>(s, srec, pad, r, fout);
+            if (!fout) dst[r] = o;
+        }
+    } else {
+        // 5F. the updated records stay in registers (record l = tid + k TPB)
+        Rec<D> u[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t l = tid + k * TPB;
+            if (l < nb) {
+                const uint32_t r = lo + l;
+                if (r >= ins_lo && r < ins_hi) {
+                    u[k] = batch_member<D, KERN, PM>(s, srec, pad, r, nullptr);
+                } else {
+                    u[k] = srec[l];
+                    dst[r] = u[k];
+                }
+            }
+        }
+        __syncthreads();
+        // 6F. the PERM words of ranks lo .. hi - 1 at step m + 1 (rank r is
+        //     slot r of that step), one Philox block per 4 ranks; they stay
+        //     in LDS until the records are written
+        uint32_t *goff = reinterpret_cast<uint32_t *>(lds);  // [256] write offset - local start
+        uint32_t *ccnt = goff + 256;                          // [256] counts, then local starts
+        uint32_t *wtmp = ccnt + 256;                          // [WT] words
+        const uint32_t q0 = lo >> 2, nq = ((hi - 1) >> 2) - q0 + 1;
+        for (uint32_t j = tid; j < nq; j += TPB) {
+            const uint4 w4 = philox4x32_10(make_uint4(q0 + j, s.m + 1, STREAM_PERM, s.sys), s.k0, s.k1);
+            wtmp[4 * j] = w4.x;
+            wtmp[4 * j + 1] = w4.y;
+            wtmp[4 * j + 2] = w4.z;
+            wtmp[4 * j + 3] = w4.w;
+        }
+        if (tid < fo.nb1) ccnt[tid] = 0;
+        __syncthreads();
+        uint32_t key[E];  // coarse digit | local index in it << 8
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t l = tid + k * TPB;
+            if (l < nb) {
+                const uint32_t c = fine_of(wtmp[lo - 4 * q0 + l], s.nbuck) >> fo.shift;
+                key[k] = c | (atomicAdd(&ccnt[c], 1u) << 8);
+            }
+        }
+        __syncthreads();
+        // the counts made here must be those of the key passes
+        if (tid < fo.nb1 && ccnt[tid] != fchk) atomicOr(flags, 1u);
+        __syncthreads();
+        if (tid < 64) (void)wave0_exclusive_scan(ccnt, ccnt, fo.nb1);
+        __syncthreads();
+        if (tid < fo.nb1) goff[tid] = fgo - ccnt[tid];
+        __syncthreads();
+        // 7F. records in coarse-digit order through LDS, R at a time, so that
+        //     consecutive lanes store to consecutive addresses
+        constexpr uint32_t R = (uint32_t)((sizeof(lds) - 2048 - WT * 4) / (sizeof(Rec<D>) + 4));
+        Rec<D> *stg = reinterpret_cast<Rec<D> *>(lds + 2048 + WT * 4);
+        uint32_t *stw = reinterpret_cast<uint32_t *>(stg + R);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t l = tid + k * TPB, r = lo + l;
+            if (l < nb && (r < ins_lo || r >= ins_hi)) {
+                const uint32_t c = key[k] & 255u;
+                fo.fixpos[r] = goff[c] + ccnt[c] + (key[k] >> 8);
+            }
+        }
+        for (uint32_t base = 0; base < nb; base += R) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const uint32_t l = tid + k * TPB;
+                if (l < nb) {
+                    const uint32_t i = ccnt[key[k] & 255u] + (key[k] >> 8) - base;
+                    if (i < R) {
+                        stg[i] = u[k];
+                        stw[i] = wtmp[lo - 4 * q0 + l];
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t cnt_r = min(R, nb - base);
+            for (uint32_t i = tid; i < cnt_r; i += TPB) {
+                const uint32_t w = stw[i];
+                const uint32_t g = goff[fine_of(w, s.nbuck) >> fo.shift] + base + i;
+                if (g < s.n) {
+                    fo.out[g] = stg[i];
+                    fo.wout[g] = w;
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -667,9 +898,12 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
 // Workgroup b-1 looks at the boundary at rank bstart[b].  The batch around it
 // is cut if the boundary is not the batch's first rank; of several
 // boundaries inside one batch only the first handles it.
+// fixpos != nullptr (fused step): the cut records are read from dst at their
+// ranks and the updated ones written to out[fixpos[rank]].
 template <int D, int KERN>
 __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__restrict__ bstart,
-                                               Rec<D> *dst, float *__restrict__ fout)
+                                               Rec<D> *dst, float *__restrict__ fout,
+                                               const uint32_t *__restrict__ fixpos, Rec<D> *out)
 {
     const uint32_t b = blockIdx.x + 1;
     const uint32_t r = bstart[b];
@@ -699,7 +933,10 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
 #pragma unroll
         for (int c = 0; c < D; ++c) o.x[c] = y[c];
         o.id = me.id;
-        dst[bs + tid] = o;
+        if (!fixpos)
+            dst[bs + tid] = o;
+        else if (fixpos[bs + tid] < s.n)  // positions are < N unless a flagged overflow left stale data
+            out[fixpos[bs + tid]] = o;
     } else if (tid < sz) {
         const Rec<D> me = sh[tid];
         float xi[D], f[D];
@@ -724,7 +961,10 @@ __global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__res
 #pragma unroll
             for (int c = 0; c < D; ++c) o.x[c] = xi[c];
             o.id = me.id;
-            dst[bs + tid] = o;
+            if (!fixpos)
+                dst[bs + tid] = o;
+            else if (fixpos[bs + tid] < s.n)
+                out[fixpos[bs + tid]] = o;
         }
     }
 }
@@ -897,16 +1137,20 @@ namespace {
 constexpr int SINGLE_TPB = 512;
 constexpr int SINGLE_CAP = RBM_SINGLE_CAP;
 constexpr int SINGLE_SBITS = 11;
-constexpr int SORT_TPB = 256;
+constexpr int SORT_TPB = 512;
 constexpr int SORT_CAP = RBM_SORT_CAP;
-constexpr int SORT_CAP_BIG = RBM_SORT_CAP_BIG;
-constexpr int SORT_SBITS = 10;
+constexpr int SORT_SBITS = 11;
 static_assert((RBM_MAX_FINE >> RBM_SPLIT_SHIFT) <= LVL_NB, "coarse buckets beyond the staging arrays");
 constexpr int DIRECT_TPB = 256;
 
 inline void mark(hipEvent_t *ev, int i, hipStream_t st)
 {
     if (ev) (void)hipEventRecord(ev[i], st);
+}
+
+inline size_t align_up(size_t x, size_t a)
+{
+    return (x + a - 1) / a * a;
 }
 
 template <typename T>
@@ -942,14 +1186,25 @@ hipError_t keys_impl(const Plan &pl, const StepArgs &s, uint32_t count, void *ws
     if (pl.nbuck > 1) {
         const KeySet q = key_set(pl, ws, 0);
         auto *flags = at<uint32_t>(ws, pl.off_flags);
+        const bool cross = pl.fuse && count > 1;
+        uint8_t *dig = cross ? at<uint8_t>(ws, pl.off_xdig) : nullptr;
+        const size_t dstride = align_up(pl.n, 256);
         hipLaunchKernelGGL(k_key_count, dim3(pl.ntf, count), dim3(1024), (size_t)pl.nbuck * 4, st, s, pl.tilef,
-                           q.kcnt);
+                           q.kcnt, pl.shift, dig, dstride);
         mark(ev, 1, st);
         hipLaunchKernelGGL(k_key_colsum, dim3((pl.nbuck + 255) / 256, count), dim3(256), 0, st, pl.ntf,
                            pl.nbuck, q.kcnt, q.ftot);
         mark(ev, 2, st);
         hipLaunchKernelGGL(k_key_starts, dim3(count), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
                            pl.cap, q.ftot, q.fstart, q.fcur, q.cstart, q.ccur, flags);
+        if (cross) {
+            // the transitions 0 -> 1, ..., count - 2 -> count - 1 of the group
+            hipLaunchKernelGGL(k_cross_count, dim3(pl.ntx, count - 1), dim3(256), 0, st, pl.nbuck, pl.nb1, pl.ntx,
+                               dstride, q.fstart, dig, at<uint16_t>(ws, pl.off_xrow),
+                               at<uint32_t>(ws, pl.off_xtsum));
+            hipLaunchKernelGGL(k_cross_scan, dim3(pl.nb1, count - 1), dim3(256), 0, st, pl.nb1, pl.ntx,
+                               at<uint32_t>(ws, pl.off_xtsum), q.cstart, at<uint32_t>(ws, pl.off_xbase));
+        }
     } else {
         mark(ev, 1, st);
         mark(ev, 2, st);
@@ -977,7 +1232,7 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS, true>),
                            dim3(1), dim3(SINGLE_TPB), 0, st, s, state, nullptr, nullptr, sorted,
-                           nullptr, flags);
+                           nullptr, flags, FuseOut<2>{});
     } else {
         auto *stage1 = at<Rec<2>>(ws, pl.off_stage1);
         auto *w1 = at<uint32_t>(ws, pl.off_w1);
@@ -991,7 +1246,9 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
             hipLaunchKernelGGL((k_scatter_coarse<2>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s,
                                pl.shift, pl.nb1, state, ccur, stage1, w1);
             mark(ev, 4, st);
-            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s,
+            StepArgs ss = s;  // the coarse scatter added the pending noise
+            ss.pssd = 0.0f;
+            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, ss,
                                pl.shift, pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
             src = stage2;
             wsrc = w2;
@@ -1001,14 +1258,9 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
             mark(ev, 4, st);
         }
         mark(ev, 5, st);
-        if (pl.cap == (uint32_t)SORT_CAP)
-            hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>),
-                               dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
-                               nullptr, flags);
-        else
-            hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, false, SORT_TPB, SORT_CAP_BIG, SORT_SBITS, true>),
-                               dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted,
-                               nullptr, flags);
+        hipLaunchKernelGGL((k_sort_step<2, K_GAUSS, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>),
+                           dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, sorted, nullptr, flags,
+                           FuseOut<2>{});
     }
     // phase A over the key-ordered records (their noise is in): c of every
     // particle, kept for phase B, and S; timed with the batch phase
@@ -1026,14 +1278,14 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
 
 // The sort kernel with the batch size fixed at compile time (unrolled member
 // loop) for the common sizes; any other p takes the runtime loop.
-template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB>
+template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB, bool FUSED = false>
 void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const Rec<D> *src,
                  const uint32_t *wsrc, const uint32_t *bstart, Rec<D> *dst, float *fout,
-                 uint32_t *flags)
+                 uint32_t *flags, const FuseOut<D> &fo = FuseOut<D>{})
 {
-#define RBM_SORT(PMM)                                                                                   \
-    hipLaunchKernelGGL((k_sort_step<D, KERN, SINGLE, TPB, CAP, SB, false, PMM>), grid, dim3(TPB), 0, st, s, \
-                       src, wsrc, bstart, dst, fout, flags)
+#define RBM_SORT(PMM)                                                                                          \
+    hipLaunchKernelGGL((k_sort_step<D, KERN, SINGLE, TPB, CAP, SB, false, PMM, FUSED>), grid, dim3(TPB), 0, st, \
+                       s, src, wsrc, bstart, dst, fout, flags, fo)
     switch (p) {
     case 2: RBM_SORT(2); break;
     case 4: RBM_SORT(4); break;
@@ -1045,7 +1297,7 @@ void launch_sort(uint32_t p, dim3 grid, hipStream_t st, const StepArgs &s, const
 
 template <int D, int KERN>
 hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, void *dst_state,
-                   float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready)
+                   float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready, uint32_t fuse)
 {
     auto *state = at<Rec<D>>(ws, pl.off_state);
     auto *dst = reinterpret_cast<Rec<D> *>(dst_state);
@@ -1057,7 +1309,10 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         hipError_t e = keys_impl(pl, s, 1, ws, st, ev);
         if (e != hipSuccess) return e;
         set = 0;
+        fuse = 0;
     }
+    if (!pl.fuse || fout || set + 1 >= pl.kb) fuse &= ~2u;
+    if (!pl.fuse || fout) fuse &= ~1u;
     if (pl.nbuck == 1) {
         for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         launch_sort<D, KERN, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS>(
@@ -1076,10 +1331,17 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     if (split) {
         auto *stage2 = at<Rec<D>>(ws, pl.off_stage2);
         auto *w2 = at<uint32_t>(ws, pl.off_w2);
-        hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s, pl.shift,
-                           pl.nb1, state, ccur, stage1, w1);
+        // the pending noise is added by the first kernel that reads the
+        // records: the coarse scatter, or the split when the previous step's
+        // sort wrote the coarse buckets
+        StepArgs ss = s;
+        if (!(fuse & 1u)) {
+            hipLaunchKernelGGL((k_scatter_coarse<D>), dim3(pl.ntiles), dim3(SCATTER_TPB), 0, st, s, pl.shift,
+                               pl.nb1, state, ccur, stage1, w1);
+            ss.pssd = 0.0f;
+        }
         mark(ev, 4, st);
-        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
+        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, ss, pl.shift,
                            pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
         mark(ev, 5, st);
         src = stage2;
@@ -1091,30 +1353,46 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         mark(ev, 4, st);
         mark(ev, 5, st);
     }
-    if (pl.cap == (uint32_t)SORT_CAP)
-        launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
-                                                                    fstart, dst, fout, flags);
-    else  // the largest systems: 1024-record buckets, the generic batch loop
-        hipLaunchKernelGGL((k_sort_step<D, KERN, false, SORT_TPB, SORT_CAP_BIG, SORT_SBITS, false, 0>),
-                           dim3(pl.nbuck), dim3(SORT_TPB), 0, st, s, src, wsrc, fstart, dst, fout, flags);
+    if (fuse & 2u) {
+        // the updated records go to the coarse buckets of the next step
+        // (key set set + 1), placed by the cross counts of this transition
+        FuseOut<D> fo;
+        fo.xrow = at<uint16_t>(ws, pl.off_xrow) + (size_t)set * pl.nbuck * pl.nb1;
+        fo.xbase = at<uint32_t>(ws, pl.off_xbase) + (size_t)set * pl.ntx * pl.nb1;
+        fo.fixpos = at<uint32_t>(ws, pl.off_fixpos);
+        fo.out = stage1;
+        fo.wout = w1;
+        fo.nb1 = pl.nb1;
+        fo.shift = pl.shift;
+        launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
+                                                                          fstart, dst, nullptr, flags, fo);
+        mark(ev, 6, st);
+        hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, nullptr,
+                           fo.fixpos, stage1);
+        mark(ev, 7, st);
+        return hipGetLastError();
+    }
+    launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc, fstart,
+                                                                dst, fout, flags);
     mark(ev, 6, st);
-    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, fout);
+    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, fout,
+                       (const uint32_t *)nullptr, (Rec<D> *)nullptr);
     mark(ev, 7, st);
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t step_d(const Plan &pl, const StepArgs &s, int kernel, void *ws, hipStream_t st,
-                  void *dst, float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready)
+                  void *dst, float *fout, hipEvent_t *ev, uint32_t set, bool keys_ready, uint32_t fuse)
 {
     switch (kernel) {
-    case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
-    case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
-    case K_LINEAR: return step_dk<D, K_LINEAR>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    case K_GAUSS: return step_dk<D, K_GAUSS>(pl, s, ws, st, dst, fout, ev, set, keys_ready, fuse);
+    case K_SOFTCOULOMB: return step_dk<D, K_SOFTCOULOMB>(pl, s, ws, st, dst, fout, ev, set, keys_ready, fuse);
+    case K_LINEAR: return step_dk<D, K_LINEAR>(pl, s, ws, st, dst, fout, ev, set, keys_ready, fuse);
     case K_HAMILTON:
-        if constexpr (D == 2) return step_dk<D, K_HAMILTON>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+        if constexpr (D == 2) return step_dk<D, K_HAMILTON>(pl, s, ws, st, dst, fout, ev, set, keys_ready, fuse);
         return hipErrorInvalidValue;
-    default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev, set, keys_ready);
+    default: return step_dk<D, K_ATTREP>(pl, s, ws, st, dst, fout, ev, set, keys_ready, fuse);
     }
 }
 
@@ -1158,13 +1436,13 @@ hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *
 
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set,
-                       bool keys_ready)
+                       bool keys_ready, uint32_t fuse)
 {
     if (keys_ready && set >= pl.kb) return hipErrorInvalidValue;
     switch (d) {
-    case 1: return step_d<1>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
-    case 2: return step_d<2>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
-    default: return step_d<3>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready);
+    case 1: return step_d<1>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready, fuse);
+    case 2: return step_d<2>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready, fuse);
+    default: return step_d<3>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready, fuse);
     }
 }
 

@@ -11,17 +11,16 @@
 // Capacity of the one-workgroup path (the whole system in LDS, 75 KB at
 // d = 3).
 #define RBM_SINGLE_CAP 2816
-// Fine buckets average at most RBM_BUCKET_MEAN records (957 at N = 2^24)
-// while that needs at most RBM_MAX_FINE buckets (N <= 31,457,280); a sort
-// workgroup then holds up to RBM_SORT_CAP (10 standard deviations above the
-// mean; a fuller bucket is reported, not dropped) in 20 KB of LDS, so eight
-// workgroups share a CU.  Above that N the RBM_MAX_FINE buckets average up to
-// 1024 records and the sort holds up to RBM_SORT_CAP_BIG (15 standard
-// deviations).
-#define RBM_BUCKET_MEAN 960
-#define RBM_SORT_CAP 1270
-#define RBM_SORT_CAP_BIG 1520
-#define RBM_KEY_SETS 8
+// Fine buckets average at most RBM_BUCKET_MEAN records (1900 at N = 2^24;
+// every N up to RBM_MAX_N needs fewer than RBM_MAX_FINE buckets); a sort
+// workgroup of 512 threads holds up to RBM_SORT_CAP (about 10 standard
+// deviations above the mean; a fuller bucket is reported, not dropped) in
+// 37 KB of LDS, so four workgroups share a CU.  Buckets this large keep the
+// coarse buckets few (69 at N = 2^24), so the runs that a scatter writes per
+// coarse bucket are long.
+#define RBM_BUCKET_MEAN 1920
+#define RBM_SORT_CAP 2368
+#define RBM_KEY_SETS 16
 #define RBM_MAX_FINE 32768
 // Scatter and split workgroups: threads holding a fixed number of records
 // each, staged through LDS a few per thread at a time.  The coarse scatter
@@ -38,6 +37,9 @@
 #define RBM_TILE (RBM_SCATTER_P * RBM_SCATTER_TPB)
 #define RBM_CHUNK (RBM_SPLIT_P * RBM_SPLIT_TPB)
 #define RBM_SPLIT_SHIFT 7
+// Fused steps: fine buckets per tile of the cross counts (records of a tile
+// of step m's fine buckets counted by their coarse bucket of step m + 1).
+#define RBM_CROSS_G 8
 
 namespace rbm {
 
@@ -55,10 +57,16 @@ struct Plan {
     uint32_t tilef;   // slots per key-count tile
     uint32_t ntf;     // key-count tiles
     uint32_t kb;      // key sets: the key passes of up to kb consecutive steps run as one launch
-    uint32_t cap;     // records a sort workgroup holds: RBM_SORT_CAP or RBM_SORT_CAP_BIG
+    uint32_t cap;     // records a sort workgroup holds (RBM_SORT_CAP)
+    // fused steps (split level present, no control variate): inside a group
+    // of steps sharing the key passes, the sort kernel of step m writes its
+    // updated records straight into the coarse buckets of step m + 1
+    bool fuse;
+    uint32_t ntx;     // cross-count tiles of RBM_CROSS_G fine buckets
     size_t rec_bytes;
     size_t off_state, off_scratch, off_stage1, off_w1, off_stage2, off_w2;
     size_t off_kcnt, off_ftot, off_fstart, off_fcur, off_cstart, off_ccur, off_flags;
+    size_t off_xrow, off_xtsum, off_xbase, off_fixpos, off_xdig;
     // control variate (cv != 0)
     int cv;
     size_t off_sorted, off_cvc, off_cvmaster, off_cvam, off_cvav, off_cvwb, off_cvspart, off_cvS;
@@ -67,15 +75,21 @@ struct Plan {
 };
 
 // Key passes (bucket counts, totals, starts and run cursors) of steps s.m ..
-// s.m + count - 1 into key sets 0 .. count - 1 (count <= pl.kb).  ev: the
-// first four phase events of the step that starts the group (may be null).
+// s.m + count - 1 into key sets 0 .. count - 1 (count <= pl.kb); with
+// pl.fuse also the cross counts and coarse write offsets of the transitions
+// between consecutive sets of the group.  ev: the first four phase events of
+// the step that starts the group (may be null).
 hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
                        hipEvent_t *ev);
 // One step with the keys of key set `set`; keys_ready == false computes
-// them first (into that set).
+// them first (into that set).  fuse (pl.fuse only, keys_ready, set + 1 <
+// group for bit 1): bit 0, the coarse buckets of this step were written by
+// the previous step's sort kernel (no coarse scatter; the split adds the
+// pending noise); bit 1, this step's sort kernel writes the coarse buckets of
+// the next step (key set set + 1) instead of the slot-ordered state.
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set = 0,
-                       bool keys_ready = false);
+                       bool keys_ready = false, uint32_t fuse = 0);
 hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *slots, void *ws,
                        hipStream_t st);
 // x != NULL: positions by id, with the pending noise of s added.

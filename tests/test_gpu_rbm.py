@@ -214,10 +214,10 @@ def test_force_mse_follows_lemma_3_1(name, n, p):
 
 def test_full_size_attrep3d_step():
     """The headline size N = 2^24, p = 8, run as the benchmark runs it (9 steps
-    in one call: a group of 8 steps sharing one launch of the key passes,
-    then one more): the slot order after every step bit-exact (the oracle
-    chains its permutations), then one more step from the GPU's state,
-    every particle within 1e-5."""
+    in one call sharing one launch of the key passes; the sort kernels of the
+    first 8 write the next step's coarse buckets): the slot order after every
+    step bit-exact (the oracle chains its permutations), then one more step
+    from the GPU's state, every particle within 1e-5."""
     w = rbm_inputs.params_of("attrep3d-n2^24-p8")
     say("full size", w["n"])
     ctx, x0 = start(w)
@@ -236,12 +236,13 @@ def test_full_size_attrep3d_step():
     assert e_rel(x10, xo) <= 1e-5
 
 
-@pytest.mark.parametrize("n,p", [(1 << 25, 3), (31457280, 8), (31457281, 8)])
+@pytest.mark.parametrize("n,p", [(1 << 25, 3), (245760, 8), (245761, 8)])
 def test_largest_supported_size(n, p):
-    """N = 2^25 (the largest the plan supports: 32768 fine buckets of 1024
-    records on average, the larger sort capacity), p = 3 with a remainder of
-    2; and the two sides of the largest N whose buckets average at most 960
-    records: permutation bit-exact and e1 <= 1e-5."""
+    """N = 2^25 (the largest the plan supports: 17536 fine buckets of 1913
+    records on average), p = 3 with a remainder of 2; and the two sides of
+    the switch to the split level (128 fine buckets of 1920 records, then
+    256 of 960 in two coarse buckets): permutation bit-exact and
+    e1 <= 1e-5."""
     w = rbm_inputs.params_of("dyson1d-n2^20-p2", n=n, p=p)
     say("max size", w["n"], w["p"])
     ctx, x0 = start(w)
