@@ -136,7 +136,7 @@ rbm_status rbm_step(rbm_ctx *ctx, void *stream);
  * nsteps times).  The bucket counts and starts of a step depend only on the
  * step index and the slot indices, so they are computed for groups of up to
  * 16 consecutive steps with one launch of each key kernel.  For N above
- * 245,760 (more than 128 fine buckets), the sort kernel of each step but a
+ * 217,600 (more than 128 fine buckets), the sort kernel of each step but a
  * group's last writes its records straight into the next step's coarse
  * buckets (one pass over the records fewer); setting the environment
  * variable RBM_FUSE=0 before rbm_init selects the unfused order. */

@@ -295,7 +295,7 @@ const char *rbm_last_error(void)
 // coarse digits.
 static rbm_status check_plan(const Plan &pl)
 {
-    if (pl.nbuck > RBM_MAX_FINE || pl.nb1 > (RBM_MAX_FINE >> RBM_SPLIT_SHIFT))
+    if (pl.nbuck > RBM_MAX_FINE || pl.nb1 > RBM_MAX_COARSE)
         return fail(RBM_ERR_UNSUPPORTED, "N = %u needs %u fine buckets (at most %d)", pl.n, pl.nbuck, RBM_MAX_FINE);
     return RBM_OK;
 }

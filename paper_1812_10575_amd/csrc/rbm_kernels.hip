@@ -4,7 +4,7 @@
 // One step m, with the particles held as records (x, id) in "slot" order
 // (the order left by the previous step).  Slot k draws the PERM word w_k; the
 // key (w_k << 32 | id) orders the particles.  The word range is cut into B
-// equal "fine buckets", f = floor(w B / 2^32) (about 1920 records each),
+// equal "fine buckets", f = floor(w B / 2^32) (about 1700 records each),
 // grouped 2^shift at a time into coarse buckets.
 //
 //   k_key_count      per tile of slots, fine-bucket histogram of the words
@@ -138,7 +138,8 @@ using LvlScatter = Lvl<RBM_SCATTER_TPB, RBM_SCATTER_P, RBM_LVL_RPT>;
 using LvlSplit = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_P, RBM_SPLIT_RPT>;
 constexpr int SCATTER_TPB = LvlScatter::TPB;
 constexpr int SPLIT_TPB = LvlSplit::TPB;
-constexpr int LVL_NB = 256;            // largest digit count of a level
+constexpr int LVL_NB = RBM_MAX_COARSE; // largest digit count of a level
+static_assert(LVL_NB <= 256, "coarse digits are stored in one byte");
 
 // dig != nullptr (fused steps): also the coarse digit of every slot, one
 // byte each, key set y at dig + y * dstride.
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(256) void k_cross_count(uint32_t nbuck, uint32_t nb
                                                      uint16_t *__restrict__ xrow,
                                                      uint32_t *__restrict__ xtsum)
 {
-    __shared__ uint32_t hist[XG * 256];
+    __shared__ uint32_t hist[XG * LVL_NB];
     __shared__ uint32_t bnd[XG + 1];
     const uint32_t t = blockIdx.y, x = blockIdx.x, tid = threadIdx.x;
     fstart += (size_t)t * (nbuck + 1);
@@ -297,18 +298,20 @@ __global__ __launch_bounds__(256) void k_cross_count(uint32_t nbuck, uint32_t nb
     for (uint32_t i = tid; i < XG * nb1; i += 256) hist[i] = 0;
     if (tid <= ng) bnd[tid] = fstart[f0 + tid];
     __syncthreads();
+    // bucket by bucket, four digits per load (aligned words: the digits of a
+    // key set are padded to a multiple of 256 bytes; a word that straddles
+    // two buckets is read by both)
     for (uint32_t g = 0; g < ng; ++g) {
-        const uint32_t b1 = bnd[g + 1];
+        const uint32_t b0 = bnd[g], b1 = bnd[g + 1];
         uint32_t *h = hist + g * nb1;
-        uint32_t k = bnd[g] + tid;
-        for (; k + 768 < b1; k += 1024) {
-            const uint32_t c0 = dig[k], c1 = dig[k + 256], c2 = dig[k + 512], c3 = dig[k + 768];
-            atomicAdd(&h[c0], 1u);
-            atomicAdd(&h[c1], 1u);
-            atomicAdd(&h[c2], 1u);
-            atomicAdd(&h[c3], 1u);
+        for (uint32_t q = (b0 >> 2) + tid; b0 < b1 && 4 * q < b1; q += 256) {
+            const uint32_t v = reinterpret_cast<const uint32_t *>(dig)[q];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t k = 4 * q + j;
+                if (k >= b0 && k < b1) atomicAdd(&h[(v >> (8 * j)) & 255u], 1u);
+            }
         }
-        for (; k < b1; k += 256) atomicAdd(&h[dig[k]], 1u);
     }
     __syncthreads();
     uint16_t *row = xrow + (size_t)f0 * nb1;
@@ -661,11 +664,10 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
     constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
     __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
-    // fused output: 2 KB of per-digit arrays, the Philox words of the
-    // bucket's ranks (WT: at most CAP + 6 of them, in blocks of 4), the
-    // staging rounds
+    // fused output: two per-digit arrays, the Philox words of the bucket's
+    // ranks (WT: at most CAP + 6 of them, in blocks of 4), the staging rounds
     constexpr size_t WT = 4 * ((CAP + 6) / 4 + 1);
-    static_assert(2048 + WT * 4 + 64 * (sizeof(Rec<D>) + 4) <= sizeof(lds), "fused staging does not fit");
+    static_assert(8 * LVL_NB + WT * 4 + 64 * (sizeof(Rec<D>) + 4) <= sizeof(lds), "fused staging does not fit");
     __shared__ uint32_t scan_tmp[TPB / 64];
     uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
     uint32_t *idv = wv + CAP;
@@ -822,16 +824,13 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         // 6F. the PERM words of ranks lo .. hi - 1 at step m + 1 (rank r is
         //     slot r of that step), one Philox block per 4 ranks; they stay
         //     in LDS until the records are written
-        uint32_t *goff = reinterpret_cast<uint32_t *>(lds);  // [256] write offset - local start
-        uint32_t *ccnt = goff + 256;                          // [256] counts, then local starts
+        uint32_t *goff = reinterpret_cast<uint32_t *>(lds);  // [LVL_NB] write offset - local start
+        uint32_t *ccnt = goff + LVL_NB;                       // [LVL_NB] counts, then local starts
         uint32_t *wtmp = ccnt + 256;                          // [WT] words
         const uint32_t q0 = lo >> 2, nq = ((hi - 1) >> 2) - q0 + 1;
         for (uint32_t j = tid; j < nq; j += TPB) {
-            const uint4 w4 = philox4x32_10(make_uint4(q0 + j, s.m + 1, STREAM_PERM, s.sys), s.k0, s.k1);
-            wtmp[4 * j] = w4.x;
-            wtmp[4 * j + 1] = w4.y;
-            wtmp[4 * j + 2] = w4.z;
-            wtmp[4 * j + 3] = w4.w;
+            reinterpret_cast<uint4 *>(wtmp)[j] =
+                philox4x32_10(make_uint4(q0 + j, s.m + 1, STREAM_PERM, s.sys), s.k0, s.k1);
         }
         if (tid < fo.nb1) ccnt[tid] = 0;
         __syncthreads();
@@ -852,25 +851,29 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         __syncthreads();
         if (tid < fo.nb1) goff[tid] = fgo - ccnt[tid];
         __syncthreads();
+        // key: the record's position in coarse-digit order (its digit's
+        // local start plus its index in the digit); the global position is
+        // goff[digit] + key
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (tid + k * TPB < nb) key[k] = ccnt[key[k] & 255u] + (key[k] >> 8);
         // 7F. records in coarse-digit order through LDS, R at a time, so that
         //     consecutive lanes store to consecutive addresses
-        constexpr uint32_t R = (uint32_t)((sizeof(lds) - 2048 - WT * 4) / (sizeof(Rec<D>) + 4));
-        Rec<D> *stg = reinterpret_cast<Rec<D> *>(lds + 2048 + WT * 4);
+        constexpr uint32_t R = (uint32_t)((sizeof(lds) - 8 * LVL_NB - WT * 4) / (sizeof(Rec<D>) + 4));
+        Rec<D> *stg = reinterpret_cast<Rec<D> *>(lds + 8 * LVL_NB + WT * 4);
         uint32_t *stw = reinterpret_cast<uint32_t *>(stg + R);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const uint32_t l = tid + k * TPB, r = lo + l;
-            if (l < nb && (r < ins_lo || r >= ins_hi)) {
-                const uint32_t c = key[k] & 255u;
-                fo.fixpos[r] = goff[c] + ccnt[c] + (key[k] >> 8);
-            }
+            if (l < nb && (r < ins_lo || r >= ins_hi))
+                fo.fixpos[r] = goff[fine_of(wtmp[lo - 4 * q0 + l], s.nbuck) >> fo.shift] + key[k];
         }
         for (uint32_t base = 0; base < nb; base += R) {
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const uint32_t l = tid + k * TPB;
                 if (l < nb) {
-                    const uint32_t i = ccnt[key[k] & 255u] + (key[k] >> 8) - base;
+                    const uint32_t i = key[k] - base;
                     if (i < R) {
                         stg[i] = u[k];
                         stw[i] = wtmp[lo - 4 * q0 + l];
@@ -895,28 +898,35 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
 // ---------------------------------------------------------------------------
 // batches cut by bucket boundaries
 // ---------------------------------------------------------------------------
-// Workgroup b-1 looks at the boundary at rank bstart[b].  The batch around it
-// is cut if the boundary is not the batch's first rank; of several
-// boundaries inside one batch only the first handles it.
+// Teams of T = 2^tsh threads (T >= the largest batch, 2p - 1), 128 / T per
+// workgroup: team j of workgroup x looks at the boundary at rank bstart[b],
+// b = x 128 / T + j + 1 <= nbound.  The batch around it is cut if the
+// boundary is not the batch's first rank; of several boundaries inside one
+// batch only the first handles it.
 // fixpos != nullptr (fused step): the cut records are read from dst at their
 // ranks and the updated ones written to out[fixpos[rank]].
 template <int D, int KERN>
-__global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__restrict__ bstart,
-                                               Rec<D> *dst, float *__restrict__ fout,
+__global__ __launch_bounds__(128) void k_fixup(StepArgs s, const uint32_t *__restrict__ bstart, uint32_t nbound,
+                                               uint32_t tsh, Rec<D> *dst, float *__restrict__ fout,
                                                const uint32_t *__restrict__ fixpos, Rec<D> *out)
 {
-    const uint32_t b = blockIdx.x + 1;
-    const uint32_t r = bstart[b];
-    if (r == 0 || r >= s.n) return;
-    uint32_t bs, be;
-    batch_of(s, r, bs, be);
-    if (r == bs) return;
-    if (bstart[b - 1] > bs) return;
-    __shared__ Rec<D> sh[128];
+    __shared__ Rec<D> shall[128];
+    const uint32_t team = threadIdx.x >> tsh, tid = threadIdx.x & ((1u << tsh) - 1u);
+    const uint32_t b = blockIdx.x * (128u >> tsh) + team + 1;
+    bool act = false;
+    uint32_t bs = 0, be = 0;
+    if (b <= nbound) {
+        const uint32_t r = bstart[b];
+        if (r != 0 && r < s.n) {
+            batch_of(s, r, bs, be);
+            act = r != bs && bstart[b - 1] <= bs;
+        }
+    }
+    Rec<D> *sh = shall + (team << tsh);
     const uint32_t sz = be - bs;
-    const uint32_t tid = threadIdx.x;
-    if (tid < sz) sh[tid] = dst[bs + tid];
+    if (act && tid < sz) sh[tid] = dst[bs + tid];
     __syncthreads();
+    if (!act) return;
     if (tid < sz && pair_flow_scheme(s) && !fout && sz == 2) {
         // a pair moves by its exact flow (the same operations as in the sort kernel)
         const Rec<D> me = sh[tid];
@@ -1140,7 +1150,8 @@ constexpr int SINGLE_SBITS = 11;
 constexpr int SORT_TPB = 512;
 constexpr int SORT_CAP = RBM_SORT_CAP;
 constexpr int SORT_SBITS = 11;
-static_assert((RBM_MAX_FINE >> RBM_SPLIT_SHIFT) <= LVL_NB, "coarse buckets beyond the staging arrays");
+static_assert((RBM_MAX_FINE >> RBM_SPLIT_SHIFT) <= LVL_NB && (1 << RBM_SPLIT_SHIFT) <= LVL_NB,
+              "digits beyond the staging arrays");
 constexpr int DIRECT_TPB = 256;
 
 inline void mark(hipEvent_t *ev, int i, hipStream_t st)
@@ -1276,6 +1287,22 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
     return hipGetLastError();
 }
 
+// Fix-up teams: T = 2^fix_shift threads, the smallest power of two that
+// holds the largest batch (2p - 1 members, p <= 64); fix_groups workgroups
+// of 128 / T teams cover the nbuck - 1 boundaries.
+uint32_t fix_shift(const Plan &pl)
+{
+    uint32_t t = 0;
+    while ((1u << t) < 2 * pl.p - 1) ++t;
+    return t;
+}
+
+uint32_t fix_groups(const Plan &pl)
+{
+    const uint32_t per = 128u >> fix_shift(pl);
+    return (pl.nbuck - 1 + per - 1) / per;
+}
+
 // The sort kernel with the batch size fixed at compile time (unrolled member
 // loop) for the common sizes; any other p takes the runtime loop.
 template <int D, int KERN, bool SINGLE, int TPB, int CAP, int SB, bool FUSED = false>
@@ -1367,16 +1394,16 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS, true>(pl.p, dim3(pl.nbuck), st, s, src, wsrc,
                                                                           fstart, dst, nullptr, flags, fo);
         mark(ev, 6, st);
-        hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, nullptr,
-                           fo.fixpos, stage1);
+        hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(fix_groups(pl)), dim3(128), 0, st, s, fstart, pl.nbuck - 1,
+                           fix_shift(pl), dst, nullptr, fo.fixpos, stage1);
         mark(ev, 7, st);
         return hipGetLastError();
     }
     launch_sort<D, KERN, false, SORT_TPB, SORT_CAP, SORT_SBITS>(pl.p, dim3(pl.nbuck), st, s, src, wsrc, fstart,
                                                                 dst, fout, flags);
     mark(ev, 6, st);
-    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(pl.nbuck - 1), dim3(128), 0, st, s, fstart, dst, fout,
-                       (const uint32_t *)nullptr, (Rec<D> *)nullptr);
+    hipLaunchKernelGGL((k_fixup<D, KERN>), dim3(fix_groups(pl)), dim3(128), 0, st, s, fstart, pl.nbuck - 1,
+                       fix_shift(pl), dst, fout, (const uint32_t *)nullptr, (Rec<D> *)nullptr);
     mark(ev, 7, st);
     return hipGetLastError();
 }

@@ -11,15 +11,16 @@
 // Capacity of the one-workgroup path (the whole system in LDS, 75 KB at
 // d = 3).
 #define RBM_SINGLE_CAP 2816
-// Fine buckets average at most RBM_BUCKET_MEAN records (1900 at N = 2^24;
+// Fine buckets average at most RBM_BUCKET_MEAN records (1680 at N = 2^24;
 // every N up to RBM_MAX_N needs fewer than RBM_MAX_FINE buckets); a sort
-// workgroup of 512 threads holds up to RBM_SORT_CAP (about 10 standard
-// deviations above the mean; a fuller bucket is reported, not dropped) in
-// 37 KB of LDS, so four workgroups share a CU.  Buckets this large keep the
-// coarse buckets few (69 at N = 2^24), so the runs that a scatter writes per
-// coarse bucket are long.
-#define RBM_BUCKET_MEAN 1920
-#define RBM_SORT_CAP 2368
+// workgroup of 512 threads holds up to RBM_SORT_CAP (8.4 standard deviations
+// above the largest mean; a fuller bucket is reported, not dropped) in 32 KB
+// of LDS, four records per thread, so four workgroups share a CU and the
+// fused sort kernel fits 64 VGPRs (eight waves per SIMD).  Buckets this large
+// keep the coarse buckets few (78 at N = 2^24), so the runs that a scatter
+// writes per coarse bucket are long.
+#define RBM_BUCKET_MEAN 1700
+#define RBM_SORT_CAP 2048
 #define RBM_KEY_SETS 16
 #define RBM_MAX_FINE 32768
 // Scatter and split workgroups: threads holding a fixed number of records
@@ -37,6 +38,10 @@
 #define RBM_TILE (RBM_SCATTER_P * RBM_SCATTER_TPB)
 #define RBM_CHUNK (RBM_SPLIT_P * RBM_SPLIT_TPB)
 #define RBM_SPLIT_SHIFT 7
+// Coarse buckets (digits of the scatter level) at most: the per-digit arrays
+// of the staging levels and of the fused sort output, and the one-byte
+// coarse digits of the key passes.
+#define RBM_MAX_COARSE 256
 // Fused steps: fine buckets per tile of the cross counts (records of a tile
 // of step m's fine buckets counted by their coarse bucket of step m + 1).
 #define RBM_CROSS_G 8

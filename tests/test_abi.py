@@ -75,8 +75,8 @@ def test_plan_fits_the_kernels_at_every_size():
     """Every supported N gets a bucket plan inside the limits the step
     kernels are built for (at most 32768 fine buckets; the library refuses a
     plan beyond them): the sizes around the switch to the split level at
-    245,760, the largest N, powers of two and a log-spaced sweep."""
-    ns = {2817, 245760, 245761, 31457280, 31457281, (1 << 25) - 1, 1 << 25}
+    217,600, the largest N, powers of two and a log-spaced sweep."""
+    ns = {2817, 217600, 217601, 31457280, 31457281, (1 << 25) - 1, 1 << 25}
     ns |= {1 << k for k in range(12, 26)}
     ns |= {int(v) for v in np.geomspace(3000, 1 << 25, 200)}
     for n in sorted(ns):

@@ -236,12 +236,12 @@ def test_full_size_attrep3d_step():
     assert e_rel(x10, xo) <= 1e-5
 
 
-@pytest.mark.parametrize("n,p", [(1 << 25, 3), (245760, 8), (245761, 8)])
+@pytest.mark.parametrize("n,p", [(1 << 25, 3), (217600, 8), (217601, 8)])
 def test_largest_supported_size(n, p):
-    """N = 2^25 (the largest the plan supports: 17536 fine buckets of 1913
+    """N = 2^25 (the largest the plan supports: 19840 fine buckets of 1691
     records on average), p = 3 with a remainder of 2; and the two sides of
-    the switch to the split level (128 fine buckets of 1920 records, then
-    256 of 960 in two coarse buckets): permutation bit-exact and
+    the switch to the split level (128 fine buckets of 1700 records, then
+    256 of 850 in two coarse buckets): permutation bit-exact and
     e1 <= 1e-5."""
     w = rbm_inputs.params_of("dyson1d-n2^20-p2", n=n, p=p)
     say("max size", w["n"], w["p"])
