@@ -116,7 +116,7 @@ int kern_of(int kernel)
 Plan make_plan(const rbm_params *prm)
 {
     Plan pl{};
-    pl.kb = 1;
+    pl.kb = pl.nsets = 1;
     pl.n = (uint32_t)prm->n;
     pl.p = (uint32_t)prm->p;
     pl.nbat = pl.n / pl.p;
@@ -165,24 +165,28 @@ Plan make_plan(const rbm_params *prm)
             pl.off_stage2 = take(recs);
             pl.off_w2 = take((size_t)pl.n * 4);
         }
-        pl.kb = RBM_KEY_SETS;
-        pl.off_kcnt = take((size_t)pl.kb * pl.ntf * pl.nbuck * 4);
-        pl.off_ftot = take((size_t)pl.kb * pl.nbuck * 4);
-        pl.off_fstart = take((size_t)pl.kb * (pl.nbuck + 1) * 4);
-        pl.off_fcur = take((size_t)pl.kb * pl.nbuck * 4);
-        pl.off_cstart = take((size_t)pl.kb * (pl.nb1 + 1) * 4);
-        pl.off_ccur = take((size_t)pl.kb * pl.nb1 * 4);
         // fused steps need the split level; the control-variate step keeps
         // its own order of kernels
         const char *env = getenv("RBM_FUSE");
         pl.fuse = pl.shift > 0 && !prm->cv && !(env && env[0] == '0');
+        // groups of up to kb steps share the key passes; fused runs hold two
+        // banks of key sets, the next group's passes made before the current
+        // group's last step
+        pl.kb = RBM_KEY_SETS;
+        pl.nsets = pl.fuse ? 2 * pl.kb : pl.kb;
+        pl.off_kcnt = take((size_t)pl.nsets * pl.ntf * pl.nbuck * 4);
+        pl.off_ftot = take((size_t)pl.nsets * pl.nbuck * 4);
+        pl.off_fstart = take((size_t)pl.nsets * (pl.nbuck + 1) * 4);
+        pl.off_fcur = take((size_t)pl.nsets * pl.nbuck * 4);
+        pl.off_cstart = take((size_t)pl.nsets * (pl.nb1 + 1) * 4);
+        pl.off_ccur = take((size_t)pl.nsets * pl.nb1 * 4);
         if (pl.fuse) {
             pl.ntx = (pl.nbuck + RBM_CROSS_G - 1) / RBM_CROSS_G;
-            pl.off_xrow = take((size_t)pl.kb * pl.nbuck * pl.nb1 * 2);
-            pl.off_xtsum = take((size_t)pl.kb * pl.ntx * pl.nb1 * 4);
-            pl.off_xbase = take((size_t)pl.kb * pl.ntx * pl.nb1 * 4);
+            pl.off_xrow = take((size_t)pl.nsets * pl.nbuck * pl.nb1 * 2);
+            pl.off_xtsum = take((size_t)pl.nsets * pl.ntx * pl.nb1 * 4);
+            pl.off_xbase = take((size_t)pl.nsets * pl.ntx * pl.nb1 * 4);
             pl.off_fixpos = take((size_t)pl.n * 4);
-            pl.off_xdig = take((size_t)pl.kb * align256(pl.n));
+            pl.off_xdig = take((size_t)pl.nsets * align256(pl.n));
         }
     }
     pl.cv = prm->cv;
@@ -355,28 +359,55 @@ rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
     const Plan &pl = ctx->plan;
     void *state = (char *)ctx->ws + pl.off_state;
     const hipStream_t hs = (hipStream_t)stream;
-    uint32_t set = 0, group = 0;
+    // Key sets: group g of up to kb steps uses sets [bank_g kb, bank_g kb +
+    // size_g), the banks alternating when fused (pl.nsets = 2 kb).  Fused, the
+    // sort of every step but the call's last writes the next step's coarse
+    // buckets, placed by the transitions that launch_keys makes: inside a
+    // group, and from a group's last step into the next group (made with that
+    // group's key passes, before the step).  Only the call's first step runs
+    // the coarse scatter and its last leaves the state in slot order.
+    uint32_t set = 0, group = 0, bank = 0, next_group = 0;
+    bool prev_out = false;
     for (int64_t k = 0; k < nsteps; ++k) {
         const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)ctx->m, ctx->pending);
         hipEvent_t *ev = nullptr;
         if (ctx->trec < ctx->tmax) ev = ctx->ev + (size_t)ctx->trec++ * (RBM_NPHASES + 1);
+        bool keys_timed = false;
         if (set == group) {
-            // the key passes of the next group of steps, in one launch each
-            group = (uint32_t)std::min<int64_t>(pl.kb, nsteps - k);
             set = 0;
-            hipError_t e = rbm::launch_keys(pl, s, group, ctx->ws, hs, ev);
+            if (next_group) {
+                // made before the previous group's last step
+                group = next_group;
+                bank ^= 1u;
+                next_group = 0;
+            } else {
+                // the key passes of the next group of steps, in one launch each
+                group = (uint32_t)std::min<int64_t>(pl.kb, nsteps - k);
+                hipError_t e = rbm::launch_keys(pl, s, group, ctx->ws, hs, ev, 0);
+                if (e != hipSuccess) return hip_fail(e, "rbm_step key launch");
+                keys_timed = true;
+            }
+        }
+        const uint32_t cur = bank * pl.kb + set;
+        const bool out = pl.fuse && k + 1 < nsteps;
+        if (out && set + 1 == group) {
+            // the next group's key passes into the other bank, and the
+            // transition from this step into its first step (timed with this step)
+            next_group = (uint32_t)std::min<int64_t>(pl.kb, nsteps - k - 1);
+            const uint32_t nb = (bank ^ 1u) * pl.kb;
+            const StepArgs sn = make_args(&ctx->prm, pl, (uint32_t)ctx->m + 1, s.ssd != 0.0f);
+            hipError_t e = rbm::launch_keys(pl, sn, next_group, ctx->ws, hs, keys_timed ? nullptr : ev, nb, cur);
             if (e != hipSuccess) return hip_fail(e, "rbm_step key launch");
-        } else if (ev) {
-            // this step's share of the key passes was timed with the group's first step
+            if (!keys_timed && ev) keys_timed = true;
+        }
+        if (!keys_timed && ev) {
+            // this step's share of the key passes was timed with another step
             for (int i = 0; i < 4; ++i) (void)hipEventRecord(ev[i], hs);
         }
-        // inside a group the sort of each step but the last writes the next
-        // step's coarse buckets; the group's last step leaves the state in
-        // slot order
-        uint32_t fuse = 0;
-        if (pl.fuse) fuse = (set > 0 ? 1u : 0u) | (set + 1 < group ? 2u : 0u);
-        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, ev, set, true, fuse);
+        const uint32_t fuse = (prev_out ? 1u : 0u) | (out ? 2u : 0u);
+        hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, ev, cur, true, fuse);
         if (e != hipSuccess) return hip_fail(e, "rbm_step launch");
+        prev_out = out;
         ++set;
         ctx->m += 1;
         ctx->pending = s.ssd != 0.0f;

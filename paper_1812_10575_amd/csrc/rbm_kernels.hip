@@ -270,13 +270,13 @@ __global__ __launch_bounds__(1024) void k_key_starts(uint32_t nbuck, uint32_t nb
 }
 
 // ---------------------------------------------------------------------------
-// cross counts of a fused transition (key set t -> t + 1, t = blockIdx.y):
-// the records of step m + t at ranks [fstart_t[f], fstart_t[f + 1]) are the
-// slots of fine bucket f; the sort kernel of that bucket writes each of them
-// into its coarse bucket of step m + t + 1, the digit that the key count
-// stored for that slot.  Per tile of RBM_CROSS_G fine buckets: xrow[f][c]
-// (records of bucket f headed for coarse bucket c) and the tile's column sums
-// xtsum[x][c].
+// cross counts of fused transitions: transition t = blockIdx.y goes from the
+// key set at fstart + t (step m) to the one at dig + t (step m + 1).  The
+// records of step m at ranks [fstart[f], fstart[f + 1]) are the slots of fine
+// bucket f; the sort kernel of that bucket writes each of them into its
+// coarse bucket of step m + 1, the digit that the key count stored for that
+// slot.  Per tile of RBM_CROSS_G fine buckets: xrow[f][c] (records of bucket
+// f headed for coarse bucket c) and the tile's column sums xtsum[x][c].
 // ---------------------------------------------------------------------------
 constexpr uint32_t XG = RBM_CROSS_G;
 
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_cross_count(uint32_t nbuck, uint32_t nb
     __shared__ uint32_t bnd[XG + 1];
     const uint32_t t = blockIdx.y, x = blockIdx.x, tid = threadIdx.x;
     fstart += (size_t)t * (nbuck + 1);
-    dig += (size_t)(t + 1) * dstride;  // the coarse digits of step m + t + 1
+    dig += (size_t)t * dstride;  // the coarse digits of the transition's next step
     xrow += (size_t)t * nbuck * nb1;
     xtsum += (size_t)t * ntx * nb1;
     const uint32_t f0 = x * XG;
@@ -323,9 +323,9 @@ __global__ __launch_bounds__(256) void k_cross_count(uint32_t nbuck, uint32_t nb
     }
 }
 
-// Coarse write offsets of a fused transition: xbase[x][c] = cstart_{t+1}[c]
-// + the records of tiles 0 .. x - 1 headed for coarse bucket c.  One
-// workgroup per (c, t).
+// Coarse write offsets of fused transitions: xbase[x][c] = cstart[c] (the
+// coarse starts of the transition's next step) + the records of tiles
+// 0 .. x - 1 headed for coarse bucket c.  One workgroup per (c, t).
 __global__ __launch_bounds__(256) void k_cross_scan(uint32_t nb1, uint32_t ntx,
                                                     const uint32_t *__restrict__ xtsum,
                                                     const uint32_t *__restrict__ cstart,
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_cross_scan(uint32_t nb1, uint32_t ntx,
     const uint32_t c = blockIdx.x, t = blockIdx.y;
     xtsum += (size_t)t * ntx * nb1;
     xbase += (size_t)t * ntx * nb1;
-    cstart += (size_t)(t + 1) * (nb1 + 1);
+    cstart += (size_t)t * (nb1 + 1);
     for (uint32_t i = threadIdx.x; i < 256u * PER; i += 256) a[i] = i < ntx ? xtsum[(size_t)i * nb1 + c] : 0u;
     __syncthreads();
     block_exclusive_scan<256, PER>(a, tmp);
@@ -1190,16 +1190,28 @@ KeySet key_set(const Plan &pl, void *ws, uint32_t k)
     return q;
 }
 
+// The cross kernels for `count` transitions, key sets src + t -> dst + t.
+void cross_impl(const Plan &pl, uint32_t src, uint32_t dst, uint32_t count, void *ws, hipStream_t st)
+{
+    const size_t dstride = align_up(pl.n, 256);
+    const KeySet a = key_set(pl, ws, src), b = key_set(pl, ws, dst);
+    uint16_t *xrow = at<uint16_t>(ws, pl.off_xrow) + (size_t)src * pl.nbuck * pl.nb1;
+    uint32_t *xtsum = at<uint32_t>(ws, pl.off_xtsum) + (size_t)src * pl.ntx * pl.nb1;
+    uint32_t *xbase = at<uint32_t>(ws, pl.off_xbase) + (size_t)src * pl.ntx * pl.nb1;
+    hipLaunchKernelGGL(k_cross_count, dim3(pl.ntx, count), dim3(256), 0, st, pl.nbuck, pl.nb1, pl.ntx, dstride,
+                       a.fstart, at<uint8_t>(ws, pl.off_xdig) + (size_t)dst * dstride, xrow, xtsum);
+    hipLaunchKernelGGL(k_cross_scan, dim3(pl.nb1, count), dim3(256), 0, st, pl.nb1, pl.ntx, xtsum, b.cstart, xbase);
+}
+
 hipError_t keys_impl(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
-                     hipEvent_t *ev)
+                     hipEvent_t *ev, uint32_t base = 0, uint32_t xsrc = 0xffffffffu)
 {
     mark(ev, 0, st);
     if (pl.nbuck > 1) {
-        const KeySet q = key_set(pl, ws, 0);
+        const KeySet q = key_set(pl, ws, base);
         auto *flags = at<uint32_t>(ws, pl.off_flags);
-        const bool cross = pl.fuse && count > 1;
-        uint8_t *dig = cross ? at<uint8_t>(ws, pl.off_xdig) : nullptr;
         const size_t dstride = align_up(pl.n, 256);
+        uint8_t *dig = pl.fuse ? at<uint8_t>(ws, pl.off_xdig) + (size_t)base * dstride : nullptr;
         hipLaunchKernelGGL(k_key_count, dim3(pl.ntf, count), dim3(1024), (size_t)pl.nbuck * 4, st, s, pl.tilef,
                            q.kcnt, pl.shift, dig, dstride);
         mark(ev, 1, st);
@@ -1208,14 +1220,10 @@ hipError_t keys_impl(const Plan &pl, const StepArgs &s, uint32_t count, void *ws
         mark(ev, 2, st);
         hipLaunchKernelGGL(k_key_starts, dim3(count), dim3(1024), 0, st, pl.nbuck, pl.nb1, pl.shift, pl.n,
                            pl.cap, q.ftot, q.fstart, q.fcur, q.cstart, q.ccur, flags);
-        if (cross) {
-            // the transitions 0 -> 1, ..., count - 2 -> count - 1 of the group
-            hipLaunchKernelGGL(k_cross_count, dim3(pl.ntx, count - 1), dim3(256), 0, st, pl.nbuck, pl.nb1, pl.ntx,
-                               dstride, q.fstart, dig, at<uint16_t>(ws, pl.off_xrow),
-                               at<uint32_t>(ws, pl.off_xtsum));
-            hipLaunchKernelGGL(k_cross_scan, dim3(pl.nb1, count - 1), dim3(256), 0, st, pl.nb1, pl.ntx,
-                               at<uint32_t>(ws, pl.off_xtsum), q.cstart, at<uint32_t>(ws, pl.off_xbase));
-        }
+        // the transitions base -> base + 1, ..., inside the group, and the
+        // one into it
+        if (pl.fuse && count > 1) cross_impl(pl, base, base + 1, count - 1, ws, st);
+        if (pl.fuse && xsrc < pl.nsets) cross_impl(pl, xsrc, base, 1, ws, st);
     } else {
         mark(ev, 1, st);
         mark(ev, 2, st);
@@ -1338,8 +1346,7 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
         set = 0;
         fuse = 0;
     }
-    if (!pl.fuse || fout || set + 1 >= pl.kb) fuse &= ~2u;
-    if (!pl.fuse || fout) fuse &= ~1u;
+    if (!pl.fuse || fout) fuse = 0;
     if (pl.nbuck == 1) {
         for (int i = 4; i <= 5; ++i) mark(ev, i, st);
         launch_sort<D, KERN, true, SINGLE_TPB, SINGLE_CAP, SINGLE_SBITS>(
@@ -1455,17 +1462,19 @@ hipError_t direct_d(const StepArgs &s, int kernel, const float *x, const uint32_
 }  // namespace
 
 hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
-                       hipEvent_t *ev)
+                       hipEvent_t *ev, uint32_t base, uint32_t xsrc)
 {
-    if (count < 1 || count > pl.kb) return hipErrorInvalidValue;
-    return keys_impl(pl, s, count, ws, st, ev);
+    if (count < 1 || count > pl.kb || base + count > pl.nsets) return hipErrorInvalidValue;
+    if (xsrc != 0xffffffffu && (!pl.fuse || xsrc >= pl.nsets || (xsrc >= base && xsrc < base + count)))
+        return hipErrorInvalidValue;
+    return keys_impl(pl, s, count, ws, st, ev, base, xsrc);
 }
 
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set,
                        bool keys_ready, uint32_t fuse)
 {
-    if (keys_ready && set >= pl.kb) return hipErrorInvalidValue;
+    if (keys_ready && set >= pl.nsets) return hipErrorInvalidValue;
     switch (d) {
     case 1: return step_d<1>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready, fuse);
     case 2: return step_d<2>(pl, s, kernel, ws, st, dst_state, fout, ev, set, keys_ready, fuse);

@@ -61,7 +61,8 @@ struct Plan {
     uint32_t ntiles;  // coarse-scatter tiles of RBM_TILE slots
     uint32_t tilef;   // slots per key-count tile
     uint32_t ntf;     // key-count tiles
-    uint32_t kb;      // key sets: the key passes of up to kb consecutive steps run as one launch
+    uint32_t kb;      // the key passes of up to kb consecutive steps run as one launch
+    uint32_t nsets;   // key sets in the workspace: kb, or two banks of kb with fuse
     uint32_t cap;     // records a sort workgroup holds (RBM_SORT_CAP)
     // fused steps (split level present, no control variate): inside a group
     // of steps sharing the key passes, the sort kernel of step m writes its
@@ -80,18 +81,21 @@ struct Plan {
 };
 
 // Key passes (bucket counts, totals, starts and run cursors) of steps s.m ..
-// s.m + count - 1 into key sets 0 .. count - 1 (count <= pl.kb); with
-// pl.fuse also the cross counts and coarse write offsets of the transitions
-// between consecutive sets of the group.  ev: the first four phase events of
-// the step that starts the group (may be null).
+// s.m + count - 1 into key sets base .. base + count - 1 (count <= pl.kb,
+// base + count <= pl.nsets); with pl.fuse also the coarse digits of every
+// slot and the cross counts and coarse write offsets of the transitions
+// between consecutive sets of the group, and (xsrc < pl.nsets) of the one
+// from key set xsrc (made earlier, the step before s.m) into set base.  ev:
+// four phase events (may be null).
 hipError_t launch_keys(const Plan &pl, const StepArgs &s, uint32_t count, void *ws, hipStream_t st,
-                       hipEvent_t *ev);
+                       hipEvent_t *ev, uint32_t base = 0, uint32_t xsrc = 0xffffffffu);
 // One step with the keys of key set `set`; keys_ready == false computes
-// them first (into that set).  fuse (pl.fuse only, keys_ready, set + 1 <
-// group for bit 1): bit 0, the coarse buckets of this step were written by
-// the previous step's sort kernel (no coarse scatter; the split adds the
-// pending noise); bit 1, this step's sort kernel writes the coarse buckets of
-// the next step (key set set + 1) instead of the slot-ordered state.
+// them first (into set 0).  fuse (pl.fuse and keys_ready only): bit 0, the
+// coarse buckets of this step were written by the previous step's sort
+// kernel (no coarse scatter; the split adds the pending noise); bit 1, this
+// step's sort kernel writes the coarse buckets of the next step instead of
+// the slot-ordered state, placed by the transition stored with key set
+// `set` (made by launch_keys).
 hipError_t launch_step(const Plan &pl, const StepArgs &s, int d, int kernel, void *ws,
                        hipStream_t st, void *dst_state, float *fout, hipEvent_t *ev, uint32_t set = 0,
                        bool keys_ready = false, uint32_t fuse = 0);

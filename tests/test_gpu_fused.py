@@ -1,10 +1,11 @@
 """Fused steps of one rbm_run call against the same steps taken one call at a time.
 
-Inside a group of steps that share the key passes, the sort kernel of every
-step but the group's last writes its updated records straight into the
-coarse buckets of the next step (placed by the cross counts of the key
-passes); the next step skips the coarse scatter and its split adds the
-deferred noise.  A step run on its own (rbm_step) always takes the unfused
+In one rbm_run call, the sort kernel of every step but the last writes its
+updated records straight into the coarse buckets of the next step (placed
+by the cross counts of the key passes, which groups of up to 16 steps share;
+a group's last step crosses into the next group, whose key passes are made
+in the other bank of key sets); the next step skips the coarse scatter and
+its split adds the deferred noise.  A step run on its own (rbm_step) always takes the unfused
 order, whose parity with the oracle is tested in test_gpu_rbm.py.  The two
 orders do the same arithmetic on the same records, so the bar is bit
 equality: positions (velocities for the second-order workload) and the slot
@@ -49,6 +50,7 @@ def state(ctx):
 # (the split level, which fused steps need)
 CASES = [
     ("attrep3d-n2^24-p8", {"n": 300007}, 19),              # d = 3, p = 8 unrolled, a group of 16 and three more
+    ("attrep3d-n2^24-p8", {"n": 300007, "p": 4}, 40),      # groups in both banks of key sets and back
     ("attrep3d-n2^24-p8", {"n": 1 << 20, "p": 7}, 10),     # the runtime batch loop, a remainder batch
     ("gauss2d-n1024-p2", {"n": 500000, "p": 5}, 8),
     ("dyson1d-n2^20-p2", {"n": 250000, "p": 3}, 8),        # two coarse buckets
