@@ -8,7 +8,10 @@ forces and the Euler-Maruyama update of every particle.
 
 Prints ONE JSON line.  `value` is particle-steps/s with the state already
 resident in HBM.  `roofline` is for the kernel that takes the most time per
-step, from HIP events recorded between the kernels inside the timed region.
+step, from HIP events recorded between the kernels in a second timed run of
+the same steps (`events_ms_per_step`: that run's time per step; the events
+add to it, so `value` and `ms_per_step` come from the first run, without
+them).
 `cpu_baseline` is the FP64 oracle timed on this host on one step of the same
 workload.
 """
@@ -455,7 +458,7 @@ def main() -> int:
     rbm.rbm_check(ctx)
     torch.cuda.synchronize()
 
-    rbm.rbm_timing(ctx, args.steps)
+    # the timed steps: one rbm_run call of K steps
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -464,6 +467,18 @@ def main() -> int:
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
+    rbm.rbm_check(ctx)
+
+    # the same K steps again with the library's HIP events between its
+    # kernels: the per-kernel durations of the roofline (the events
+    # themselves add to the step, so `value` comes from the run above)
+    rbm.rbm_timing(ctx, args.steps)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    rbm.rbm_run(ctx, args.steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total_ev = t_start.elapsed_time(t_end)
     phase_ms, nrec = rbm.rbm_phase_times(ctx)
     rbm.rbm_timing(ctx, 0)
     rbm.rbm_check(ctx)
@@ -481,6 +496,7 @@ def main() -> int:
         roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "kernel": dom}
     roof["phase_ms"] = {k: round(v, 5) for k, v in phase_ms.items()}
+    roof["events_ms_per_step"] = round(ms_total_ev / args.steps, 5)
     rec = 4 * (w["d"] + 1)
     roof["step_floor_frac"] = round(2 * rec * value / (HBM_PEAK_GBS * 1e9), 4)
 
