@@ -109,3 +109,19 @@ def test_status_strings():
     for st in range(6):
         assert rbm.rbm_status_str(st)
     assert rbm.rbm_status_str(99) == "unknown status"
+
+
+def test_fused_steps_size_their_buffers(monkeypatch):
+    """Fused steps (more than 128 fine buckets, no control variate) hold two
+    banks of key sets, the coarse digits of every slot, the cross counts and
+    the fix-up positions; RBM_FUSE=0 plans the unfused order without them.
+    Below the split level (N <= 217,600) there is nothing to fuse."""
+    n = 1 << 20
+    fused = rbm.rbm_workspace_size(P(n=n))
+    monkeypatch.setenv("RBM_FUSE", "0")
+    plain = rbm.rbm_workspace_size(P(n=n))
+    small_plain = rbm.rbm_workspace_size(P(n=200000))
+    monkeypatch.delenv("RBM_FUSE")
+    assert rbm.rbm_workspace_size(P(n=200000)) == small_plain
+    # at least 32 key sets of one digit byte per slot and the 4-byte fix-up table
+    assert fused - plain >= 32 * n + 4 * n
