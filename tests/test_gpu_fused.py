@@ -93,3 +93,24 @@ def test_fused_run_matches_the_oracle():
     xo, so = ora.rbm_run(o, w["p"], 0, 19, x0.astype(np.float64))
     assert np.array_equal(s, so)
     assert ora.rel_max_error(x, xo) <= 1e-4
+
+
+def test_unfused_order_gives_the_same_bits(monkeypatch):
+    """RBM_FUSE=0 (read at rbm_init) plans the unfused order: every step of
+    an rbm_run call runs the coarse scatter, groups of 16 steps share one
+    bank of key sets.  It gives the same bits as the fused run."""
+    w = rbm_inputs.params_of("attrep3d-n2^24-p8", n=300007, p=5)
+    x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"])
+    a = start(w, x0)
+    rbm.rbm_run(a, 21)
+    rbm.rbm_check(a)
+    xa, sa = state(a)
+    del a
+    monkeypatch.setenv("RBM_FUSE", "0")
+    b = start(w, x0)
+    monkeypatch.delenv("RBM_FUSE")
+    rbm.rbm_run(b, 21)
+    rbm.rbm_check(b)
+    xb, sb = state(b)
+    assert np.array_equal(sa, sb)
+    assert np.array_equal(xa.view(np.uint32), xb.view(np.uint32))
