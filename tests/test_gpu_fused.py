@@ -57,6 +57,7 @@ CASES = [
     ("dysonsplit1d-n2^20-p2", {}, 8),                      # pairs moved by their exact flow
     ("wealth1d-n2^20-p2", {}, 8),                          # multiplicative noise
     ("hamilton1d-n2^20-p2", {}, 8),                        # Verlet records (x, u)
+    ("attrep3d-n2^24-p8", {"n": 300007, "p": 64}, 5),      # the largest batch: one fix-up team per workgroup
     ("attrep3d-n2^24-p8", {}, 3),                          # the headline size
     ("dyson1d-n2^20-p2", {"n": 1 << 25, "p": 3}, 3),       # the larger sort capacity
 ]
@@ -112,5 +113,24 @@ def test_unfused_order_gives_the_same_bits(monkeypatch):
     rbm.rbm_run(b, 21)
     rbm.rbm_check(b)
     xb, sb = state(b)
+    assert np.array_equal(sa, sb)
+    assert np.array_equal(xa.view(np.uint32), xb.view(np.uint32))
+
+
+def test_fused_calls_resume_bitwise():
+    """Ten steps in one call equal four then six in two calls (each call
+    starts from and leaves the state in slot order)."""
+    w = rbm_inputs.params_of("attrep3d-n2^24-p8", n=300007, p=7)
+    x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"])
+    a = start(w, x0)
+    rbm.rbm_run(a, 10)
+    xa, sa = state(a)
+    del a
+    b = start(w, x0)
+    rbm.rbm_run(b, 4)
+    rbm.rbm_run(b, 6)
+    rbm.rbm_check(b)
+    xb, sb = state(b)
+    assert rbm.rbm_step_index(b) == 10
     assert np.array_equal(sa, sb)
     assert np.array_equal(xa.view(np.uint32), xb.view(np.uint32))
