@@ -139,7 +139,13 @@ Plan make_plan(const rbm_params *prm)
             pl.nbuck = pl.nb1 * per;
             // chunks per coarse bucket: room for the mean plus 16 standard deviations
             const double mean = (double)pl.n / pl.nb1;
-            pl.jmax = (uint32_t)std::ceil((mean + 16.0 * std::sqrt(mean) + 64.0) / RBM_CHUNK);
+            const double room = mean + 16.0 * std::sqrt(mean) + 64.0;
+            pl.chunk = RBM_CHUNK;
+            pl.jmax = (uint32_t)std::ceil(room / pl.chunk);
+            if (pl.nb1 * pl.jmax < RBM_SPLIT_FEW) {
+                pl.chunk = RBM_CHUNK_SMALL;
+                pl.jmax = (uint32_t)std::ceil(room / pl.chunk);
+            }
         }
         pl.cap = RBM_SORT_CAP;
         pl.ntiles = (pl.n + RBM_TILE - 1) / RBM_TILE;

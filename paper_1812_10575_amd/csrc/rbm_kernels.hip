@@ -16,8 +16,9 @@
 //                    coarse buckets; each (tile, bucket) run is reserved with
 //                    one atomic and written through an LDS reorder so that
 //                    lanes store to consecutive addresses
-//   k_split          each 12K-record chunk of a coarse bucket goes to its
-//                    fine buckets the same way
+//   k_split          each chunk of a coarse bucket (12K records, or 4K when
+//                    that gives too few workgroups) goes to its fine
+//                    buckets the same way
 //   k_sort_step      one workgroup per fine bucket: order it in LDS by the
 //                    unique key, evaluate the batch forces of eq. (2.3) for
 //                    every batch inside the bucket, apply the Euler-Maruyama
@@ -126,7 +127,6 @@ __device__ __forceinline__ uint32_t wave0_exclusive_scan(const uint32_t *a, uint
 // key counts: fine-bucket histogram of the PERM words, per tile of slots
 // ---------------------------------------------------------------------------
 constexpr uint32_t TILE = RBM_TILE;    // slots per coarse-scatter workgroup
-constexpr uint32_t CHUNK = RBM_CHUNK;  // records per split workgroup
 // A staging level: TPB threads holding P records each, LDS rounds of RPT
 // records per thread.
 template <int TPB_, int P_, int RPT_>
@@ -136,6 +136,7 @@ struct Lvl {
 };
 using LvlScatter = Lvl<RBM_SCATTER_TPB, RBM_SCATTER_P, RBM_LVL_RPT>;
 using LvlSplit = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_P, RBM_SPLIT_RPT>;
+using LvlSplitSmall = Lvl<RBM_SPLIT_TPB, RBM_SPLIT_SMALL_P, RBM_SPLIT_SMALL_P>;
 constexpr int SCATTER_TPB = LvlScatter::TPB;
 constexpr int SPLIT_TPB = LvlSplit::TPB;
 constexpr int LVL_NB = RBM_MAX_COARSE; // largest digit count of a level
@@ -464,9 +465,9 @@ __global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint
     staged_write<D, LvlScatter>(L, rx, rid, w, nact, s.nbuck, shift, 0xffffffffu, nb1, ccur, stage, wout);
 }
 
-// Split: chunk j of coarse bucket c (workgroup c * jmax + j) into the 2^shift
-// fine buckets of c, adding the pending noise of s.
-template <int D>
+// Split: chunk j of coarse bucket c (workgroup c * jmax + j; C::P x C::TPB
+// records) into the 2^shift fine buckets of c, adding the pending noise of s.
+template <int D, class C>
 __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
                                                    const uint32_t *__restrict__ cstart,
                                                    const Rec<D> *__restrict__ in,
@@ -476,21 +477,23 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
                                                    uint32_t *__restrict__ wout,
                                                    uint32_t *__restrict__ flags)
 {
-    __shared__ StageLds<D, LvlSplit> L;
+    static_assert(C::TPB == SPLIT_TPB, "one split block size");
+    constexpr uint32_t CH = (uint32_t)(C::P * C::TPB);
+    __shared__ StageLds<D, C> L;
     const uint32_t c = blockIdx.x / jmax, j = blockIdx.x % jmax;
     const uint32_t c0 = cstart[c], c1 = cstart[c + 1];
     // the jmax chunks must cover the coarse bucket (mean + 16 sd of room)
-    if (j == 0 && threadIdx.x == 0 && c1 - c0 > jmax * CHUNK) atomicOr(flags, 1u);
-    const uint32_t lo = min(c0 + j * CHUNK, c1);
-    const uint32_t hi = min(lo + CHUNK, c1);
+    if (j == 0 && threadIdx.x == 0 && c1 - c0 > jmax * CH) atomicOr(flags, 1u);
+    const uint32_t lo = min(c0 + j * CH, c1);
+    const uint32_t hi = min(lo + CH, c1);
     if (lo == hi) return;
-    float rx[LvlSplit::P][D];
-    uint32_t rid[LvlSplit::P], w[LvlSplit::P];
-    // thread t holds records lo + t + LvlSplit::TPB k: the valid ones are a prefix in k
+    float rx[C::P][D];
+    uint32_t rid[C::P], w[C::P];
+    // thread t holds records lo + t + C::TPB k: the valid ones are a prefix in k
     uint32_t nact = 0;
 #pragma unroll
-    for (int k = 0; k < LvlSplit::P; ++k) {
-        const uint32_t e = lo + threadIdx.x + k * LvlSplit::TPB;
+    for (int k = 0; k < C::P; ++k) {
+        const uint32_t e = lo + threadIdx.x + k * C::TPB;
         Rec<D> t{};
         w[k] = 0u;
         if (e < hi) {
@@ -506,7 +509,20 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
         rid[k] = t.id;
     }
     const uint32_t ndig = 1u << shift;
-    staged_write<D, LvlSplit>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
+    staged_write<D, C>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
+}
+
+// The split of a plan, by its chunk size.
+template <int D>
+void launch_split(const Plan &pl, hipStream_t st, const StepArgs &s, const uint32_t *cstart, const Rec<D> *in,
+                  const uint32_t *win, uint32_t *fcur, Rec<D> *out, uint32_t *wout, uint32_t *flags)
+{
+    if (pl.chunk == (uint32_t)RBM_CHUNK_SMALL)
+        hipLaunchKernelGGL((k_split<D, LvlSplitSmall>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
+                           pl.jmax, cstart, in, win, fcur, out, wout, flags);
+    else
+        hipLaunchKernelGGL((k_split<D, LvlSplit>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
+                           pl.jmax, cstart, in, win, fcur, out, wout, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,8 +1283,7 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
             mark(ev, 4, st);
             StepArgs ss = s;  // the coarse scatter added the pending noise
             ss.pssd = 0.0f;
-            hipLaunchKernelGGL((k_split<2>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, ss,
-                               pl.shift, pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
+            launch_split<2>(pl, st, ss, cstart, stage1, w1, fcur, stage2, w2, flags);
             src = stage2;
             wsrc = w2;
         } else {
@@ -1375,8 +1390,7 @@ hipError_t step_dk(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
             ss.pssd = 0.0f;
         }
         mark(ev, 4, st);
-        hipLaunchKernelGGL((k_split<D>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, ss, pl.shift,
-                           pl.jmax, cstart, stage1, w1, fcur, stage2, w2, flags);
+        launch_split<D>(pl, st, ss, cstart, stage1, w1, fcur, stage2, w2, flags);
         mark(ev, 5, st);
         src = stage2;
         wsrc = w2;

@@ -37,6 +37,12 @@
 #define RBM_SPLIT_RPT 6
 #define RBM_TILE (RBM_SCATTER_P * RBM_SCATTER_TPB)
 #define RBM_CHUNK (RBM_SPLIT_P * RBM_SPLIT_TPB)
+// A plan with fewer than RBM_SPLIT_FEW split chunks of RBM_CHUNK records
+// (N below about 2^23) splits chunks of RBM_CHUNK_SMALL instead (4 records
+// per thread, one staging round) so that more workgroups share the GPU.
+#define RBM_SPLIT_SMALL_P 4
+#define RBM_CHUNK_SMALL (RBM_SPLIT_SMALL_P * RBM_SPLIT_TPB)
+#define RBM_SPLIT_FEW 512
 #define RBM_SPLIT_SHIFT 7
 // Coarse buckets (digits of the scatter level) at most: the per-digit arrays
 // of the staging levels and of the fused sort output, and the one-byte
@@ -58,6 +64,7 @@ struct Plan {
     uint32_t nb1;     // coarse buckets
     uint32_t shift;   // log2(fine buckets per coarse bucket), 0 without a split level
     uint32_t jmax;    // split chunks per coarse bucket
+    uint32_t chunk;   // records per split chunk: RBM_CHUNK or RBM_CHUNK_SMALL
     uint32_t ntiles;  // coarse-scatter tiles of RBM_TILE slots
     uint32_t tilef;   // slots per key-count tile
     uint32_t ntf;     // key-count tiles
