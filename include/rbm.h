@@ -113,7 +113,11 @@ typedef struct {
 
 typedef struct rbm_ctx rbm_ctx;
 
-/* Bytes of device workspace rbm_init needs for these parameters. */
+/* Bytes of device workspace rbm_init needs for these parameters (about
+ * 120 B per particle at d = 3 for N above 217,600 with fused steps, of which
+ * 32 B per particle are the coarse digits of two banks of 16 key sets; the
+ * environment variable RBM_FUSE=0, read here and by rbm_init, plans the
+ * unfused order without those buffers). */
 rbm_status rbm_workspace_size(const rbm_params *prm, size_t *bytes);
 
 /* Create a context.  d_x0: [N][d] FP32 positions by id.  d_slots: NULL for
