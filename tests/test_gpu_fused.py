@@ -58,6 +58,7 @@ CASES = [
     ("wealth1d-n2^20-p2", {}, 8),                          # multiplicative noise
     ("hamilton1d-n2^20-p2", {}, 8),                        # Verlet records (x, u)
     ("attrep3d-n2^24-p8", {"n": 300007, "p": 64}, 5),      # the largest batch: one fix-up team per workgroup
+    ("attrep3d-n2^24-p8", {"n": 217601}, 6),               # the smallest N with the split level
     ("attrep3d-n2^24-p8", {}, 3),                          # the headline size
     ("dyson1d-n2^20-p2", {"n": 1 << 25, "p": 3}, 3),       # the larger sort capacity
 ]
@@ -134,3 +135,21 @@ def test_fused_calls_resume_bitwise():
     assert rbm.rbm_step_index(b) == 10
     assert np.array_equal(sa, sb)
     assert np.array_equal(xa.view(np.uint32), xb.view(np.uint32))
+
+
+def test_forces_after_a_fused_run_match_the_oracle():
+    """rbm_forces on the state a fused run leaves (slot order, pending noise
+    added by the force path) against the oracle's forces for the same
+    division."""
+    w = rbm_inputs.params_of("attrep3d-n2^24-p8", n=300007)
+    x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"])
+    ctx = start(w, x0)
+    rbm.rbm_run(ctx, 5)
+    rbm.rbm_check(ctx)
+    x, s = state(ctx)
+    f = rbm.rbm_forces(ctx, 5).cpu().numpy()
+    o = ora.Params(d=w["d"], kernel=w["kernel"], kparam=w["kparam"], beta=w["beta"],
+                   sigma=w["sigma"], dt=w["dt"], seed=w["seed"])
+    perm = ora.permutation(o, 5, s)
+    fo = ora.rbm_forces(o, w["p"], x.astype(np.float64), perm)
+    assert ora.rel_max_error(f, fo) <= 1e-5
