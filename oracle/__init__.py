@@ -19,7 +19,10 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZED=1: the ASan/UBSan build (see build.py; needs the sanitizer
+# runtime preloaded)
+_SANITIZED = os.environ.get("ORACLE_SANITIZED", "") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if _SANITIZED else "liboracle.so")
 _lib = None
 
 K_GAUSS, K_SOFTCOULOMB, K_ATTREP, K_COULOMB_SPLIT, K_WEALTH_SPLIT, K_HAMILTON = 0, 1, 2, 3, 4, 5
@@ -57,12 +60,14 @@ def _load():
         return _lib
     if not os.path.exists(_LIB_PATH):
         from . import build as _b  # noqa: WPS433 (build on first use)
-        _b.build()
+        _b.build(sanitize=_SANITIZED)
     lib = ctypes.CDLL(_LIB_PATH)
     u32p = ctypes.POINTER(ctypes.c_uint32)
     f64p = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(_Params)
     lib.ora_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.ora_set_threads.argtypes = [ctypes.c_int32]
+    lib.ora_get_threads.restype = ctypes.c_int32
     lib.ora_uniform.argtypes = [ctypes.c_uint32]
     lib.ora_uniform.restype = ctypes.c_double
     lib.ora_perm_word.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
@@ -87,6 +92,18 @@ def _load():
     lib.ora_rbmr_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, f64p]
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (results do not depend on it);
+    returns the count now in use."""
+    lib = _load()
+    lib.ora_set_threads(int(n))
+    return int(lib.ora_get_threads())
+
+
+def get_threads() -> int:
+    return int(_load().ora_get_threads())
 
 
 def _u32(a):

@@ -49,11 +49,20 @@
  *   it is uniform because the words are i.i.d. and independent of the slot
  *   order (ties on w, probability 2^-32 per pair, resolve by id).  The sorted
  *   order becomes the next step's slot order.
+ *
+ * Loops over particles (keys, batch forces, updates, direct sums) run in
+ * parallel with OpenMP when the library is built with it; each particle's
+ * arithmetic is the same written sequence of FP64 operations whatever the
+ * thread count, and the keys are unique, so every result is independent of
+ * the number of threads (ora_set_threads).
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (SC'11)                                                     */
@@ -189,17 +198,77 @@ static int cmp_u64(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* Threads of the parallel loops (OpenMP; the arithmetic of every particle
+ * is the same whatever the count, so results do not depend on it). */
+void ora_set_threads(int32_t nt)
+{
+#ifdef _OPENMP
+    if (nt > 0) omp_set_num_threads(nt);
+#else
+    (void)nt;
+#endif
+}
+
+int32_t ora_get_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Ascending sort of n distinct 64-bit keys: qsort of one run per thread,
+ * then rounds of pairwise merges.  The keys are unique, so the order is the
+ * one any correct sort gives. */
+static void sort_keys(uint64_t *keys, int64_t n)
+{
+    int64_t runs = ora_get_threads();
+    if (runs > n / 4096) runs = n / 4096;
+    if (runs < 2) {
+        qsort(keys, (size_t)n, sizeof(uint64_t), cmp_u64);
+        return;
+    }
+    int64_t *bnd = (int64_t *)malloc((size_t)(runs + 1) * sizeof(int64_t));
+    for (int64_t r = 0; r <= runs; ++r) bnd[r] = n * r / runs;
+#pragma omp parallel for schedule(static, 1)
+    for (int64_t r = 0; r < runs; ++r)
+        qsort(keys + bnd[r], (size_t)(bnd[r + 1] - bnd[r]), sizeof(uint64_t), cmp_u64);
+    uint64_t *tmp = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t *src = keys, *dst = tmp;
+    for (int64_t width = 1; width < runs; width *= 2) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t r = 0; r < runs; r += 2 * width) {
+            const int64_t lo = bnd[r];
+            const int64_t mid = bnd[r + width < runs ? r + width : runs];
+            const int64_t hi = bnd[r + 2 * width < runs ? r + 2 * width : runs];
+            int64_t a = lo, b = mid, o = lo;
+            while (a < mid && b < hi) dst[o++] = src[a] < src[b] ? src[a++] : src[b++];
+            while (a < mid) dst[o++] = src[a++];
+            while (b < hi) dst[o++] = src[b++];
+        }
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != keys) memcpy(keys, src, (size_t)n * sizeof(uint64_t));
+    free(tmp);
+    free(bnd);
+}
+
 /* slots[k] = id of the particle in slot k (input); perm[r] = id at sorted
  * rank r (output; may alias slots). */
 void ora_permutation(const ora_params *prm, int64_t n, uint32_t m,
                      const uint32_t *slots, uint32_t *perm)
 {
     uint64_t *keys = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         const uint64_t w = ora_perm_word(prm->seed, prm->sys, m, (uint32_t)k);
         keys[k] = (w << 32) | (uint64_t)slots[k];
     }
-    qsort(keys, (size_t)n, sizeof(uint64_t), cmp_u64);
+    sort_keys(keys, n);
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; ++r) perm[r] = (uint32_t)(keys[r] & 0xffffffffu);
     free(keys);
 }
@@ -226,6 +295,7 @@ void ora_rbm_forces(const ora_params *prm, int64_t n, int32_t p,
                     const double *x, const uint32_t *perm, double *f)
 {
     const int d = prm->d;
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; ++r) {
         int64_t b0, b1;
         ora_batch_of(n, p, r, &b0, &b1);
@@ -250,6 +320,7 @@ void ora_direct_forces(const ora_params *prm, int64_t n, const double *x,
                        const uint32_t *ids, int64_t nids, double *f)
 {
     const int d = prm->d;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nids; ++t) {
         const uint32_t i = ids[t];
         double acc[3] = {0.0, 0.0, 0.0};
@@ -272,6 +343,7 @@ void ora_direct_moments(const ora_params *prm, int64_t n, const double *x,
                         const uint32_t *ids, int64_t nids, double *f, double *m2)
 {
     const int d = prm->d;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nids; ++t) {
         const uint32_t i = ids[t];
         double acc[3] = {0.0, 0.0, 0.0}, acc2 = 0.0;
@@ -302,6 +374,7 @@ static void euler_update(const ora_params *prm, int64_t n, uint32_t m,
 {
     const int d = prm->d;
     const double sq = sqrt(prm->dt);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double z[4] = {0.0, 0.0, 0.0, 0.0};
         if (prm->sigma != 0.0) ora_normals(prm->seed, prm->sys, m, (uint32_t)i, z);
@@ -360,6 +433,7 @@ static void gbm_update(const ora_params *prm, int64_t n, uint32_t m, double *x)
 {
     const int d = prm->d;
     const double sq = sqrt(prm->dt), s = prm->sigma;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double z[4] = {0.0, 0.0, 0.0, 0.0};
         if (s != 0.0) ora_normals(prm->seed, prm->sys, m, (uint32_t)i, z);
@@ -378,6 +452,7 @@ static void gbm_update(const ora_params *prm, int64_t n, uint32_t m, double *x)
 static void verlet_update(const ora_params *prm, int64_t n, uint32_t m, const double *f, double *x)
 {
     const double h = m == 0 ? 0.5 * prm->dt : prm->dt;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         const double xi = x[i * 2], ui = x[i * 2 + 1];
         const double u1 = ui + h * (f[i * 2] - prm->beta * xi);
@@ -401,7 +476,8 @@ void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
     double *f = (double *)malloc((size_t)n * d * sizeof(double));
     ora_permutation(prm, n, m, slots, slots);
     if (prm->kernel == ORA_K_COULOMB_SPLIT) {
-        for (int64_t q = 0; q + 1 < n; q += 2) {
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < n - 1; q += 2) {
             const int64_t i = slots[q], j = slots[q + 1];
             double yi[3], yj[3];
             ora_pair_flow(d, prm->dt, x + i * d, x + j * d, yi, yj);
@@ -412,7 +488,8 @@ void ora_rbm_step(const ora_params *prm, int64_t n, int32_t p, uint32_t m,
         }
         for (int64_t e = 0; e < n * d; ++e) f[e] = 0.0;
     } else if (prm->kernel == ORA_K_WEALTH_SPLIT) {
-        for (int64_t q = 0; q + 1 < n; q += 2) {
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < n - 1; q += 2) {
             const int64_t i = slots[q], j = slots[q + 1];
             double yi[3], yj[3];
             ora_pair_flow_linear(d, prm->dt, prm->kparam, x + i * d, x + j * d, yi, yj);

@@ -699,3 +699,35 @@ def test_hamiltonian_rbm_error_decays_like_sqrt_tau(ora):
     for errs in (ex, exu):
         slope = np.polyfit(np.log(taus), np.log(errs), 1)[0]
         assert 0.4 < slope < 0.62, (slope, errs)
+
+
+@pytest.mark.parametrize("kern,d,p", [(2, 3, 8), (3, 1, 2), (4, 1, 2), (5, 2, 3)])
+def test_results_do_not_depend_on_the_thread_count(ora, kern, d, p):
+    """The oracle's parallel loops give the same bits on 1 and 5 threads: the
+    permutation (a parallel merge of per-thread sorted runs of the unique
+    keys against one qsort), the batch forces, every update scheme and the
+    direct sum."""
+    n = 20011 if kern not in (3, 4) else 20012
+    prm = ora.Params(d=d, kernel=kern, kparam={2: 0.01, 3: 0.0, 4: 1.0, 5: 1.0}[kern], beta=0.5,
+                     sigma=0.0 if kern == 5 else 0.3, dt=1e-3)
+    x = rbm_inputs.normal(n, d, seed=31).astype(np.float64)
+    if kern == 4:
+        x = np.abs(x) + 0.1
+    slots = np.random.default_rng(2).permutation(n).astype(np.uint32)
+    old = ora.get_threads()
+    try:
+        res = []
+        for t in (1, 5):
+            assert ora.set_threads(t) == t
+            xs, ss = ora.rbm_run(prm, p, 3, 2, x, slots)
+            fd = ora.direct_forces(prm, x[:2000], np.arange(0, 2000, 7))
+            res.append((xs, ss, fd))
+    finally:
+        ora.set_threads(old)
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][2], res[1][2])
+    # the permutation is the key order (one sequential sort of the keys)
+    w = np.array([ora.perm_word(prm.seed, prm.sys, 3, k) for k in range(n)], dtype=np.uint64)
+    keys = (w << np.uint64(32)) | slots.astype(np.uint64)
+    assert np.array_equal(ora.permutation(prm, 3, slots), (np.sort(keys) & np.uint64(0xffffffff)).astype(np.uint32))
