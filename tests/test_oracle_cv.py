@@ -128,6 +128,73 @@ def test_zero_network_is_plain_rbm():
     np.testing.assert_allclose(cv.cv_forces(z, z, x, perm, p), ora.rbm_forces(prm, p, x, perm), rtol=1e-13, atol=1e-15)
 
 
+def _plain_params(sigma):
+    import oracle as ora
+    return ora.Params(d=2, kernel=ora.K_GAUSS, kparam=0.0, beta=1.0, sigma=sigma, dt=1e-3, seed=5, sys=2)
+
+
+@pytest.mark.parametrize("n,p", [(41, 3), (64, 2), (9, 9)])
+def test_cv_step_with_zero_networks_is_the_plain_step(n, p):
+    """Zero networks make the control-variate force the plain batch force, so
+    cv_step (division, update and noise of Algorithm 1) must be the plain
+    oracle step: sigma > 0, step m > 0, a slot order that is not the
+    identity, and a last batch that takes the remainder."""
+    import oracle as ora
+    prm = _plain_params(0.5)
+    x = rbm_inputs.normal(n, 2, seed=21).astype(np.float64)
+    slots = np.random.default_rng(n).permutation(n).astype(np.uint32)
+    z = np.zeros(cv.NPARAM)
+    x1, s1 = cv.cv_step(z, z, prm, p, 7, x, slots)
+    xo, so = ora.rbm_step(prm, p, 7, x, slots)
+    assert np.array_equal(s1, so)
+    np.testing.assert_allclose(x1, xo, rtol=0, atol=1e-13)
+    # the noise is there: the step differs from the noiseless one by sigma sqrt(dt) z
+    xq, _ = ora.rbm_step(_plain_params(0.0), p, 7, x, slots)
+    zz = np.array([ora.normals(5, 2, 7, i)[:2] for i in range(n)])
+    np.testing.assert_allclose(x1 - xq, 0.5 * math.sqrt(1e-3) * zz, rtol=0, atol=1e-13)
+
+
+def test_cv_step_chain_equals_two_plain_steps():
+    import oracle as ora
+    n, p = 50, 4
+    prm = _plain_params(0.5)
+    x = rbm_inputs.normal(n, 2, seed=22).astype(np.float64)
+    slots = np.random.default_rng(1).permutation(n).astype(np.uint32)
+    z = np.zeros(cv.NPARAM)
+    x1, s1 = cv.cv_step(z, z, prm, p, 3, x, slots)
+    x2, s2 = cv.cv_step(z, z, prm, p, 4, x1, s1)
+    xo, so = ora.rbm_run(prm, p, 3, 2, x, slots)
+    assert np.array_equal(s2, so)
+    np.testing.assert_allclose(x2, xo, rtol=0, atol=1e-13)
+
+
+def test_cv_step_moves_by_the_cv_force(thetas):
+    """With trained-like networks the step keeps the plain step's division and
+    noise and replaces only the force: x1(theta) - x1(0) = dt (F_cv - F_plain)
+    on the same division; and averaged over every division of a tiny system
+    the control-variate force is the direct force (Lemma 3.1 for K_res),
+    which the noiseless step then applies."""
+    import oracle as ora
+    n, p = 8, 2
+    prm = _plain_params(0.5)
+    x = rbm_inputs.normal(n, 2, seed=23).astype(np.float64)
+    slots = np.arange(n, dtype=np.uint32)
+    z = np.zeros(cv.NPARAM)
+    ta, tc = thetas
+    xa, sa = cv.cv_step(ta, tc, prm, p, 2, x, slots)
+    xz, sz = cv.cv_step(z, z, prm, p, 2, x, slots)
+    assert np.array_equal(sa, sz)
+    fcv = cv.cv_forces(ta, tc, x, sa, p)
+    fpl = ora.rbm_forces(prm, p, x, sa)
+    np.testing.assert_allclose((xa - xz) / 1e-3, fcv - fpl, rtol=1e-9, atol=1e-9)
+    mean = np.zeros((n, 2))
+    cnt = 0
+    for div in divisions(n, p):
+        mean += cv.cv_forces(ta, tc, x, np.concatenate(div), p)
+        cnt += 1
+    np.testing.assert_allclose(mean / cnt, ora.direct_forces(prm, x), rtol=1e-11, atol=1e-13)
+
+
 def test_adam_first_step_closed_form():
     g = np.array([0.3, -2.0, 1e-3, 0.0])
     th, m, v = cv.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
