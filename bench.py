@@ -12,8 +12,8 @@ step, from HIP events recorded between the kernels in a second timed run of
 the same steps (`events_ms_per_step`: that run's time per step; the events
 add to it, so `value` and `ms_per_step` come from the first run, without
 them).
-`cpu_baseline` is the FP64 oracle timed on this host on one step of the same
-workload.
+`cpu_baseline` is the FP64 oracle timed on this host on whole steps of the
+same workload, on all the host threads the process may use and on one.
 """
 from __future__ import annotations
 
@@ -121,26 +121,49 @@ def direct_rate(w, x0) -> dict:
                          "frac": round(tf / FP32_PEAK_TFLOPS, 4), "flops_per_pair": DIRECT_FLOPS_PER_PAIR}}
 
 
+def host_threads() -> int:
+    """Host threads this process may use: the CPUs it is allowed to run on,
+    capped by OMP_NUM_THREADS when that is set (the GPU machine sets it to its
+    CPU share)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def cpu_baseline(w: dict, x0) -> dict:
-    """The FP64 oracle on this host: whole steps of the same workload,
-    repeated until at least 10 s have passed."""
+    """The FP64 oracle on this host: whole steps of the same workload on all
+    the host threads this process may use (the value), then on one thread,
+    each repeated until a few seconds have passed.  The oracle's results do
+    not depend on the thread count."""
     import numpy as np
     import oracle as ora
     o = ora.Params(d=w["d"], kernel=w["kernel"], kparam=w["kparam"], beta=w["beta"],
                    sigma=w["sigma"], dt=w["dt"], seed=w["seed"])
-    x = x0.astype(np.float64)
-    slots = np.arange(w["n"], dtype=np.uint32)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        x, slots = ora.rbm_step(o, w["p"], steps, x, slots)
-        steps += 1
-        t = time.perf_counter() - t0
-        if t >= 10.0:
-            break
-    return {"value": w["n"] * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the same workload (N={w['n']}, p={w['p']}), "
-                      f"single-threaded FP64 C oracle, {t:.1f} s"}
+
+    def timed(threads: int, min_s: float):
+        used = ora.set_threads(threads)
+        x = x0.astype(np.float64)
+        slots = np.arange(w["n"], dtype=np.uint32)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            x, slots = ora.rbm_step(o, w["p"], steps, x, slots)
+            steps += 1
+            t = time.perf_counter() - t0
+            if t >= min_s:
+                return w["n"] * steps / t, steps, t, used
+
+    nt = host_threads()
+    v_all, s_all, t_all, used = timed(nt, 8.0)
+    v_one, s_one, t_one, _ = timed(1, 8.0)
+    return {"value": v_all, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{s_all} full steps of the same workload (N={w['n']}, p={w['p']}) on {used} threads "
+                      f"(OpenMP over particles, parallel merge sort of the keys), {t_all:.1f} s; "
+                      f"single thread: {s_one} steps, {t_one:.1f} s",
+            "single_thread": {"value": v_one, "cores": 1, "steps": s_one, "seconds": round(t_one, 2)},
+            "os_cpu_count": os.cpu_count()}
 
 
 def force_mse(args) -> dict:
@@ -268,8 +291,8 @@ def dyson_split(args) -> dict:
     the analytic density at the end."""
     import numpy as np
     import torch
-    import oracle as ora
     import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import measure
     import rbm_inputs
     w = rbm_inputs.params_of("dysonsplit1d-n2^20-p2")
     prm = rbm.Params(**{k: w[k] for k in FIELDS})
@@ -283,11 +306,11 @@ def dyson_split(args) -> dict:
     rbm.rbm_check(ctx)
     x = rbm.rbm_positions(ctx).cpu().numpy()[:, 0].astype(np.float64)
     t_end = w["steps"] * w["dt"]
-    sig = 1 + math.exp(-2 * t_end)
-    ks = ora.ks_distance(x, lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig)))
+    radius = measure.dyson_radius(t_end)
+    ks = measure.ks_distance(x, lambda v: measure.semicircle_cdf(v, radius))
     return {"workload": "dysonsplit1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": t_end,
             "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
-            "ks_vs_analytic": ks, "m2": float(np.mean(x * x)), "m2_analytic": sig / 2}
+            "ks_vs_analytic": ks, "m2": measure.second_moment(x), "m2_analytic": radius * radius / 4}
 
 
 def wealth(args) -> dict:
@@ -297,8 +320,8 @@ def wealth(args) -> dict:
     law of shape 2 and scale the mean wealth."""
     import numpy as np
     import torch
-    import oracle as ora
     import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import measure
     import rbm_inputs
     w = rbm_inputs.params_of("wealth1d-n2^20-p2")
     prm = rbm.Params(**{k: w[k] for k in FIELDS})
@@ -314,7 +337,7 @@ def wealth(args) -> dict:
     eta = float(y.mean())
     return {"workload": "wealth1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": w["steps"] * w["dt"],
             "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
-            "mean_wealth": eta, "ks_vs_inverse_gamma": ora.ks_distance(y, lambda v: ora.inverse_gamma_cdf(v, 2.0, eta))}
+            "mean_wealth": eta, "ks_vs_inverse_gamma": measure.ks_distance(y, lambda v: measure.inverse_gamma_cdf(v, 2.0, eta))}
 
 
 def rbmr(args) -> dict:
@@ -325,8 +348,8 @@ def rbmr(args) -> dict:
     and the KS distance to the analytic density at the end."""
     import numpy as np
     import torch
-    import oracle as ora
     import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import measure
     import rbm_inputs
     w = rbm_inputs.params_of("dysonrbmr1d-n2^20-p2")
     prm = rbm.Params(**{k: w[k] for k in FIELDS})
@@ -341,12 +364,12 @@ def rbmr(args) -> dict:
     dt = time.perf_counter() - t0
     y = x.cpu().numpy()[:, 0].astype(np.float64)
     t_end = w["steps"] * w["dt"]
-    sig = 1 + math.exp(-2 * t_end)
+    radius = measure.dyson_radius(t_end)
     return {"workload": "dysonrbmr1d-n2^20-p2", "n": w["n"], "iterations": w["steps"] * per, "t": t_end,
             "value": (w["steps"] - 10) * per * w["p"] / dt, "unit": "particle-steps/s",
             "us_per_window": 1e6 * dt / (w["steps"] - 10),
-            "ks_vs_analytic": ora.ks_distance(y, lambda v: ora.semicircle_cdf_r(v, math.sqrt(2 * sig))),
-            "m2": float(np.mean(y * y)), "m2_analytic": sig / 2}
+            "ks_vs_analytic": measure.ks_distance(y, lambda v: measure.semicircle_cdf(v, radius)),
+            "m2": measure.second_moment(y), "m2_analytic": radius * radius / 4}
 
 
 def hamilton(args) -> dict:
@@ -358,8 +381,8 @@ def hamilton(args) -> dict:
     bounds it by C(T) sqrt(tau/(p-1)))."""
     import numpy as np
     import torch
-    import oracle as ora
     import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import measure
     import rbm_inputs
     w = rbm_inputs.params_of("hamilton1d-n2^20-p2")
     prm = rbm.Params(**{k: w[k] for k in FIELDS})
@@ -387,9 +410,9 @@ def hamilton(args) -> dict:
             c = rbm.rbm_init(rbm.Params(**{k: dict(ws, dt=tau, seed=seed)[k] for k in FIELDS}),
                              torch.from_numpy(x0).cuda())
             rbm.rbm_run(c, int(round(1.0 / tau)))
-            e2.append(ora.rms_error(rbm.rbm_positions(c).cpu().numpy()[:, 0], xr) ** 2)
+            e2.append(measure.rms_error(rbm.rbm_positions(c).cpu().numpy()[:, 0], xr) ** 2)
         errs.append(math.sqrt(float(np.mean(e2))))
-    slope = float(np.polyfit(np.log(taus), np.log(errs), 1)[0])
+    slope = measure.loglog_slope(taus, errs)
     return {"workload": "hamilton1d-n2^20-p2", "n": w["n"], "steps": w["steps"], "t": w["steps"] * w["dt"],
             "value": w["n"] * (w["steps"] - 10) / dt, "unit": "particle-steps/s",
             "error_n": n, "error_taus": taus, "rms_position_error": errs, "slope": slope}
@@ -400,6 +423,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5, help="timed calls of --steps steps; the median is the value")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -458,15 +482,25 @@ def main() -> int:
     rbm.rbm_check(ctx)
     torch.cuda.synchronize()
 
-    # the timed steps: one rbm_run call of K steps
+    # the timed steps: one rbm_run call of K steps, repeated (the run goes
+    # on from where the last call stopped); the median call is the value
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    rbm.rbm_run(ctx, args.steps)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms_total = t_start.elapsed_time(t_end)
+
+    def timed_call(k):
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        rbm.rbm_run(ctx, k)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end)
+
+    runs = [timed_call(args.steps) for _ in range(args.repeats)]
+    ms_total = sorted(runs)[len(runs) // 2]
+    # a call's first step also scatters the records into their first coarse
+    # buckets (later steps find them there): the cost of a one-step call,
+    # and the per-step cost inside a call without it
+    one = sorted(timed_call(1) for _ in range(5))[2]
     rbm.rbm_check(ctx)
 
     # the same K steps again with the library's HIP events between its
@@ -499,6 +533,11 @@ def main() -> int:
     roof["events_ms_per_step"] = round(ms_total_ev / args.steps, 5)
     rec = 4 * (w["d"] + 1)
     roof["step_floor_frac"] = round(2 * rec * value / (HBM_PEAK_GBS * 1e9), 4)
+    timing = {"repeats": args.repeats, "ms_per_call": [round(v, 4) for v in runs],
+              "ms_per_step_min": round(min(runs) / args.steps, 5), "ms_per_step_max": round(max(runs) / args.steps, 5),
+              "ms_one_step_call": round(one, 5)}
+    if args.steps > 1:
+        timing["ms_per_step_after_first"] = round((ms_total - one) / (args.steps - 1), 5)
 
     out = {
         "metric": METRIC,
@@ -517,6 +556,7 @@ def main() -> int:
                    "kernel": ["-x exp(-|x|^2)", "x/(|x|^2+a)", "x/(|x|^2+a)-x"][w["kernel"]],
                    "a": w["kparam"], "beta": w["beta"], "sigma": w["sigma"], "dt": w["dt"]},
         "roofline": roof,
+        "timing": timing,
     }
     if not args.no_sweep:
         out["p_sweep"] = p_sweep(args, w, x0)
