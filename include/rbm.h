@@ -378,6 +378,25 @@ rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t ro
 rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window,
                     int32_t rounds, void *d_ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rbmr_run
+ * with its workspace taken from a buffer inside the library instead of a
+ * caller argument.  The buffer is a static device array of
+ * RBM_NOALLOC_SCRATCH_BYTES per GPU (held from the first call on that GPU
+ * until the process ends); its address is resolved once per device.  The
+ * call allocates nothing (no hipMalloc, no allocating library routine).
+ * Same arguments, limits, results (bit for bit) and errors as rbmr_run;
+ * RBM_ERR_WORKSPACE when rbmr_workspace_size(prm, window, rounds) exceeds
+ * RBM_NOALLOC_SCRATCH_BYTES (e.g. d <= 2 fits N up to 2^21 with the default
+ * window, d = 3 up to 2^20).  Every call on one GPU shares that GPU's
+ * buffer: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and give undefined results; calls in one stream
+ * order are safe.  Nothing of a call's buffer contents is carried into the
+ * next call. */
+#define RBM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rbm_status rbmr_run_noalloc(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window,
+                            int32_t rounds, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

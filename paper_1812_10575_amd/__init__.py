@@ -26,13 +26,14 @@ SYMBOLS = (
     "direct_forces", "direct_step", "rbm_status_str", "rbm_last_error",
     "cv_init", "cv_set_weights", "cv_get_weights", "cv_features", "cv_grads", "cv_train",
     "rbm_force_sqerr", "ensemble_workspace_size", "ensemble_run", "direct_moments",
-    "rbmr_workspace_size", "rbmr_run",
+    "rbmr_workspace_size", "rbmr_run", "rbmr_run_noalloc",
 )
 ENS_LDS = 4096
 ENS_MAXN = 256 * 1024
 CV_NPARAM = 6432
 RBMR_MAX_P = 8
 RBMR_MAX_WINDOW = 1 << 22
+NOALLOC_SCRATCH_BYTES = 64 << 20
 RBM_K_GAUSS, RBM_K_SOFTCOULOMB, RBM_K_ATTREP, RBM_K_COULOMB_SPLIT, RBM_K_WEALTH_SPLIT, RBM_K_HAMILTON = range(6)
 PHASES = ("keycount", "keysum", "keystarts", "scatter", "split", "sort", "fixup")
 
@@ -102,6 +103,7 @@ def lib():
                          ctypes.POINTER(rbm_ensemble_tile), vp, sz, ctypes.c_int32, vp],
         "rbmr_workspace_size": [pp, i64, ctypes.c_int32, ctypes.POINTER(sz)],
         "rbmr_run": [pp, vp, i64, i64, i64, ctypes.c_int32, vp, sz, vp],
+        "rbmr_run_noalloc": [pp, vp, i64, i64, i64, ctypes.c_int32, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -310,6 +312,15 @@ def rbmr_run(prm: Params, x, k0: int, niter: int, window: int = 0, rounds: int =
         ws = torch.empty(need, dtype=torch.uint8, device=x.device)
     _check(lib().rbmr_run(ctypes.byref(prm.c()), _ptr(x), k0, niter, window, rounds, _ptr(ws), ws.numel(),
                           _stream(stream)))
+    return x
+
+
+def rbmr_run_noalloc(prm: Params, x, k0: int, niter: int, window: int = 0, rounds: int = 0, stream=None):
+    """rbmr_run with the library's static per-GPU workspace (no allocation by
+    the library or here); returns x."""
+    import torch
+    _expect(x, torch.float32, (prm.n, prm.d), "x")
+    _check(lib().rbmr_run_noalloc(ctypes.byref(prm.c()), _ptr(x), k0, niter, window, rounds, _stream(stream)))
     return x
 
 

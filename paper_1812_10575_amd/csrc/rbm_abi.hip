@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/rbm.h"
@@ -961,18 +962,8 @@ static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t round
     return RBM_OK;
 }
 
-rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes)
-{
-    if (!bytes) return fail(RBM_ERR_INVALID, "bytes is NULL");
-    rbm::RbmrLayout lay;
-    const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
-    if (st != RBM_OK) return st;
-    *bytes = lay.bytes;
-    return RBM_OK;
-}
-
-rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window, int32_t rounds,
-                    void *d_ws, size_t ws_bytes, void *stream)
+static rbm_status rbmr_run_ws(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window,
+                              int32_t rounds, void *d_ws, size_t ws_bytes, void *stream)
 {
     rbm::RbmrLayout lay;
     const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
@@ -996,6 +987,65 @@ rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter
     const hipError_t e = rbm::rbmr_launch(a, prm->d, prm->kernel, lay, d_ws, d_x, (uint64_t)k0, (uint64_t)niter,
                                           (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "rbmr_run launch");
+}
+
+// The workspace of rbmr_run_noalloc: one static array per GPU.  In host code
+// its name stands for the array but is not its device address; the address
+// is resolved once per device (with that device current) by
+// hipGetSymbolAddress and only that pointer is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[RBM_NOALLOC_SCRATCH_BYTES];
+
+static rbm_status noalloc_scratch(void **out)
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *addr[MAXDEV] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "rbmr_run_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= MAXDEV) return fail(RBM_ERR_UNSUPPORTED, "device %d above the %d supported", dev, MAXDEV);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "rbmr_run_noalloc: hipGetSymbolAddress");
+        if (!p || ((uintptr_t)p & 255u) != 0) return fail(RBM_ERR_HIP, "rbmr_run_noalloc: bad scratch address");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return RBM_OK;
+}
+
+
+rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes)
+{
+    if (!bytes) return fail(RBM_ERR_INVALID, "bytes is NULL");
+    rbm::RbmrLayout lay;
+    const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
+    if (st != RBM_OK) return st;
+    *bytes = lay.bytes;
+    return RBM_OK;
+}
+
+rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window, int32_t rounds,
+                    void *d_ws, size_t ws_bytes, void *stream)
+{
+    return rbmr_run_ws(prm, d_x, k0, niter, window, rounds, d_ws, ws_bytes, stream);
+}
+
+rbm_status rbmr_run_noalloc(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter, int64_t window,
+                            int32_t rounds, void *stream)
+{
+    rbm::RbmrLayout lay;
+    const rbm_status st = rbmr_plan(prm, window, rounds, &lay);
+    if (st != RBM_OK) return st;
+    if (lay.bytes > RBM_NOALLOC_SCRATCH_BYTES)
+        return fail(RBM_ERR_WORKSPACE, "this run needs %zu bytes of workspace, above the %zu of the static buffer",
+                    lay.bytes, (size_t)RBM_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    const rbm_status sst = noalloc_scratch(&ws);
+    if (sst != RBM_OK) return sst;
+    return rbmr_run_ws(prm, d_x, k0, niter, window, rounds, ws, RBM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"
