@@ -205,8 +205,8 @@ def test_cv_force_is_unbiased_on_the_gpu():
 
 def test_trained_network_beats_plain_rbm():
     """Train on pairs from the run's own trajectory (plain RBM-1), then the
-    force MSE against the direct sum, averaged over divisions, is smaller
-    with the control variate than without it at the same p."""
+    force MSE against the direct sum, averaged over divisions, is at least 50
+    times smaller with the control variate than without it at the same p."""
     n, p = 1 << 15, 2
     w = wl(n=n, p=p)
     plain = rbm.rbm_init(gp(w, 0), torch.from_numpy(rbm_inputs.workload(w["init"], n, w["seed"])).cuda())
@@ -217,7 +217,7 @@ def test_trained_network_beats_plain_rbm():
     snap = torch.stack(snaps)
     x = snaps[-1]
     ctx = rbm.rbm_init(gp(w, 1), x)
-    losses = rbm.cv_train(ctx, snap, 400, 4096, lr=2e-3).cpu().numpy()
+    losses = rbm.cv_train(ctx, snap, 2000, 8192, lr=2e-3).cpu().numpy()
     say("loss", losses[:3], losses[-3:])
     assert losses[-20:].mean() < 0.25 * losses[:20].mean()
     ids = torch.from_numpy(np.random.default_rng(0).choice(n, 2048, replace=False).astype(np.int32)).cuda()
@@ -230,4 +230,6 @@ def test_trained_network_beats_plain_rbm():
             acc += float(rbm.rbm_force_sqerr(f, ids, fdir).cpu()[0])
         mse[name] = acc / (16 * ids.numel())
     say("force MSE", mse, "gain", mse["plain"] / mse["cv"])
-    assert mse["cv"] < 0.5 * mse["plain"]
+    # the full-size workload (2^22 particles, 4096 Adam steps of 16384 pairs)
+    # measures a gain of about 550; this shorter training must reach 50
+    assert mse["cv"] < mse["plain"] / 50.0
