@@ -241,9 +241,16 @@ rbm_status cv_grads(rbm_ctx *ctx, const float *d_x, const float *d_y, int64_t np
 rbm_status cv_train(rbm_ctx *ctx, const float *d_snap, int32_t nsnap, int64_t nsteps,
                     int32_t batch, float lr, float *d_loss, void *stream);
 
-/* Measurement: d_out[0] = sum over t < nids of |d_f[d_ids[t]] - d_fref[t]|^2
- * (d components each, FP64, fixed summation order).  d_f: [N][d] by id. */
-rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids,
+/* Measurement of the force error of Lemma 3.1 on a subset: d_out[0] =
+ * sum over t < nids of |d_f[d_ids[t]] - d_fref[t]|^2 (d components each,
+ * summed in FP64 in a fixed order, so the result does not depend on the
+ * launch).  d_f: [n][d] forces by id (e.g. from rbm_forces), d_fref:
+ * [nids][d] reference forces (e.g. direct_forces of the same ids), d_out: one
+ * double.  An id >= n is not read: it makes d_out[0] NaN.  nids = 0 gives 0
+ * (d_ids and d_fref may then be NULL).
+ * Errors: RBM_ERR_INVALID for NULL pointers, d outside 1..3, n < 1 or
+ * n > 2^31 - 1, nids < 0 or nids > 2^30. */
+rbm_status rbm_force_sqerr(const float *d_f, int64_t n, const uint32_t *d_ids, int64_t nids,
                            const float *d_fref, int32_t d, double *d_out, void *stream);
 
 /* ---- batched ensemble -----------------------------------------------------

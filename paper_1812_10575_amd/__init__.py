@@ -97,7 +97,7 @@ def lib():
         "cv_features": [vp, vp, i64, vp, vp, vp],
         "cv_grads": [vp, vp, vp, i64, vp, vp, vp],
         "cv_train": [vp, vp, ctypes.c_int32, i64, ctypes.c_int32, ctypes.c_float, vp, vp],
-        "rbm_force_sqerr": [vp, vp, i64, vp, ctypes.c_int32, vp, vp],
+        "rbm_force_sqerr": [vp, i64, vp, i64, vp, ctypes.c_int32, vp, vp],
         "ensemble_workspace_size": [ctypes.POINTER(rbm_ensemble), vp, ctypes.POINTER(sz)],
         "ensemble_run": [ctypes.POINTER(rbm_ensemble), vp, vp, vp, i64, i64,
                          ctypes.POINTER(rbm_ensemble_tile), vp, sz, ctypes.c_int32, vp],
@@ -380,14 +380,21 @@ def cv_train(ctx: "Context", snap, nsteps: int, batch: int, lr: float = 1e-3, st
 
 
 def rbm_force_sqerr(f, ids, fref, stream=None):
-    """sum_t |f[ids[t]] - fref[t]|^2 in FP64 (returns a 1-element CUDA tensor)."""
+    """sum_t |f[ids[t]] - fref[t]|^2 in FP64 (returns a 1-element CUDA tensor).
+    f: [n][d] float32 forces by id; ids: int32 [nids], each in 0..n-1;
+    fref: [nids][d] float32."""
     import torch
-    d = f.shape[1]
+    if f.dim() != 2:
+        raise ValueError(f"f: need a [n][d] tensor, got shape {tuple(f.shape)}")
+    n, d = int(f.shape[0]), int(f.shape[1])
+    _expect(f, torch.float32, (n, d), "f")
     nids = ids.numel()
     _expect(ids, torch.int32, (nids,), "ids")
     _expect(fref, torch.float32, (nids, d), "fref")
+    if nids and (int(ids.min()) < 0 or int(ids.max()) >= n):
+        raise ValueError(f"ids must lie in 0..{n - 1}")
     out = torch.empty(1, dtype=torch.float64, device=f.device)
-    _check(lib().rbm_force_sqerr(_ptr(f), _ptr(ids), nids, _ptr(fref), d, _ptr(out), _stream(stream)))
+    _check(lib().rbm_force_sqerr(_ptr(f), n, _ptr(ids), nids, _ptr(fref), d, _ptr(out), _stream(stream)))
     return out
 
 

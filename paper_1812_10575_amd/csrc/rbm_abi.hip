@@ -641,12 +641,13 @@ rbm_status cv_train(rbm_ctx *ctx, const float *d_snap, int32_t nsnap, int64_t ns
     return RBM_OK;
 }
 
-rbm_status rbm_force_sqerr(const float *d_f, const uint32_t *d_ids, int64_t nids, const float *d_fref, int32_t d,
-                           double *d_out, void *stream)
+rbm_status rbm_force_sqerr(const float *d_f, int64_t n, const uint32_t *d_ids, int64_t nids, const float *d_fref,
+                           int32_t d, double *d_out, void *stream)
 {
-    if (!d_f || !d_ids || !d_fref || !d_out) return fail(RBM_ERR_INVALID, "NULL pointer argument");
-    if (d < 1 || d > 3 || nids < 0 || nids > (1LL << 30)) return fail(RBM_ERR_INVALID, "bad sizes");
-    hipError_t e = rbm::launch_sqerr(d_f, d_ids, (uint32_t)nids, d_fref, d, d_out, (hipStream_t)stream);
+    if (!d_f || !d_out || (nids > 0 && (!d_ids || !d_fref))) return fail(RBM_ERR_INVALID, "NULL pointer argument");
+    if (d < 1 || d > 3 || n < 1 || n > 0x7fffffffLL || nids < 0 || nids > (1LL << 30))
+        return fail(RBM_ERR_INVALID, "bad sizes");
+    hipError_t e = rbm::launch_sqerr(d_f, (uint32_t)n, d_ids, (uint32_t)nids, d_fref, d, d_out, (hipStream_t)stream);
     return e == hipSuccess ? RBM_OK : hip_fail(e, "rbm_force_sqerr");
 }
 

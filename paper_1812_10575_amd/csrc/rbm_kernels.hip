@@ -1042,8 +1042,9 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v)
 }
 
 // out[0] = sum_t |f[ids[t]] - fref[t]|^2 in FP64: one workgroup, each thread
-// a strided FP64 partial, then a fixed-order tree.
-__global__ __launch_bounds__(1024) void k_sqerr(const float *__restrict__ f,
+// a strided FP64 partial, then a fixed-order tree.  An id >= n is not read
+// and makes the sum NaN.
+__global__ __launch_bounds__(1024) void k_sqerr(const float *__restrict__ f, uint32_t n,
                                                 const uint32_t *__restrict__ ids, uint32_t nids,
                                                 const float *__restrict__ fref, int d,
                                                 double *__restrict__ out)
@@ -1051,9 +1052,13 @@ __global__ __launch_bounds__(1024) void k_sqerr(const float *__restrict__ f,
     __shared__ double part[1024];
     double acc = 0.0;
     for (uint32_t t = threadIdx.x; t < nids; t += 1024) {
-        const size_t i = ids[t];
+        const uint32_t i = ids[t];
+        if (i >= n) {
+            acc = __builtin_nan("");
+            continue;
+        }
         for (int c = 0; c < d; ++c) {
-            const double e = (double)f[i * d + c] - (double)fref[(size_t)t * d + c];
+            const double e = (double)f[(size_t)i * d + c] - (double)fref[(size_t)t * d + c];
             acc += e * e;
         }
     }
@@ -1530,10 +1535,10 @@ hipError_t launch_fill(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_sqerr(const float *f, const uint32_t *ids, uint32_t nids, const float *fref, int d,
+hipError_t launch_sqerr(const float *f, uint32_t n, const uint32_t *ids, uint32_t nids, const float *fref, int d,
                         double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sqerr, dim3(1), dim3(1024), 0, st, f, ids, nids, fref, d, out);
+    hipLaunchKernelGGL(k_sqerr, dim3(1), dim3(1024), 0, st, f, n, ids, nids, fref, d, out);
     return hipGetLastError();
 }
 

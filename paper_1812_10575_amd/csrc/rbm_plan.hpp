@@ -112,7 +112,7 @@ hipError_t launch_init(const Plan &pl, int d, const float *x0, const uint32_t *s
 hipError_t launch_positions(const Plan &pl, const StepArgs &s, int d, const void *ws, float *x,
                             uint32_t *ids, hipStream_t st);
 hipError_t launch_fill(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
-hipError_t launch_sqerr(const float *f, const uint32_t *ids, uint32_t nids, const float *fref, int d,
+hipError_t launch_sqerr(const float *f, uint32_t n, const uint32_t *ids, uint32_t nids, const float *fref, int d,
                         double *out, hipStream_t st);
 // m2 (force mode only, may be null): 1/(N-1) sum_j |K(X_i - X_j)|^2 per target
 hipError_t launch_direct(const StepArgs &s, int d, int kernel, const float *x,
