@@ -46,20 +46,27 @@ namespace rbm {
 // ---------------------------------------------------------------------------
 // scans
 // ---------------------------------------------------------------------------
+// Inclusive scan across the 64 lanes of a wavefront (every lane active):
+// within each row of 16 lanes by DPP row shifts of 1, 2, 4 and 8 (lanes
+// shifted in from outside the row add 0), then each row adds the totals of
+// the rows before it, read from lanes 15, 31 and 47.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    const uint32_t r0 = __builtin_amdgcn_readlane(v, 15);
+    const uint32_t r1 = __builtin_amdgcn_readlane(v, 31);
+    const uint32_t r2 = __builtin_amdgcn_readlane(v, 47);
+    const uint32_t row = (threadIdx.x & 63u) >> 4;
+    return v + (row >= 1u ? r0 : 0u) + (row >= 2u ? r1 : 0u) + (row >= 3u ? r2 : 0u);
 }
 
-// Exclusive scan of a[0..TPB*PER) in LDS, in place; returns the total.
-// `tmp` holds TPB/64 words of LDS.  Ends with a barrier.
-template <int TPB, int PER>
+// Exclusive scan of a[0..TPB*PER) in LDS, in place; returns the total (and
+// stores it at a[TPB*PER] if STORE_TOTAL).  `tmp` holds TPB/64 words of LDS.
+// Ends with a barrier.
+template <int TPB, int PER, bool STORE_TOTAL = false>
 __device__ uint32_t block_exclusive_scan(uint32_t *a, uint32_t *tmp)
 {
     const int tid = threadIdx.x;
@@ -86,6 +93,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t *a, uint32_t *tmp)
         a[tid * PER + k] = run;
         run += v[k];
     }
+    if (STORE_TOTAL && tid == 0) a[TPB * PER] = total;
     __syncthreads();
     return total;
 }
@@ -441,6 +449,15 @@ __global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint
     const uint32_t end = min(base + TILE, s.n);
     float rx[LvlScatter::P][D];
     uint32_t rid[LvlScatter::P], w[LvlScatter::P];
+    // all loads first (indices clamped into the tile), then the words and
+    // the pending noise
+    Rec<D> t[LvlScatter::P];
+#pragma unroll
+    for (int g = 0; g < LvlScatter::P / 4; ++g) {
+        const uint32_t k = base + 4 * (threadIdx.x + g * LvlScatter::TPB);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[4 * g + j] = state[min(k + j, end - 1u)];
+    }
     uint32_t nact = 0;
 #pragma unroll
     for (int g = 0; g < LvlScatter::P / 4; ++g) {
@@ -448,14 +465,10 @@ __global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint
         const uint4 w4 = philox4x32_10(make_uint4(k >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            Rec<D> t{};
-            if (k + j < end) {
-                t = state[k + j];
-                add_pending_noise<D>(s, t.x, t.id);
-            }
+            if (k + j < end) add_pending_noise<D>(s, t[4 * g + j].x, t[4 * g + j].id);
 #pragma unroll
-            for (int c = 0; c < D; ++c) rx[4 * g + j][c] = t.x[c];
-            rid[4 * g + j] = t.id;
+            for (int c = 0; c < D; ++c) rx[4 * g + j][c] = t[4 * g + j].x[c];
+            rid[4 * g + j] = t[4 * g + j].id;
             w[4 * g + j] = j == 0 ? w4.x : (j == 1 ? w4.y : (j == 2 ? w4.z : w4.w));
         }
         // slots are consecutive per thread and groups ascend, so the valid
@@ -489,24 +502,28 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
     if (lo == hi) return;
     float rx[C::P][D];
     uint32_t rid[C::P], w[C::P];
-    // thread t holds records lo + t + C::TPB k: the valid ones are a prefix in k
+    // thread t holds records lo + t + C::TPB k: the valid ones are a prefix in k.
+    // Every load is issued before any is used (indices clamped into the
+    // chunk), so a thread has all of its records in flight at once.
+    Rec<D> t[C::P];
+#pragma unroll
+    for (int k = 0; k < C::P; ++k) {
+        const uint32_t e = min(lo + threadIdx.x + k * C::TPB, hi - 1u);
+        t[k] = in[e];
+        w[k] = win[e];
+    }
     uint32_t nact = 0;
 #pragma unroll
     for (int k = 0; k < C::P; ++k) {
-        const uint32_t e = lo + threadIdx.x + k * C::TPB;
-        Rec<D> t{};
-        w[k] = 0u;
-        if (e < hi) {
-            t = in[e];
+        if (lo + threadIdx.x + k * C::TPB < hi) {
             // records written by a fused sort still lack the previous step's
             // noise (the host clears s.pssd when the coarse scatter added it)
-            add_pending_noise<D>(s, t.x, t.id);
-            w[k] = win[e];
+            add_pending_noise<D>(s, t[k].x, t[k].id);
             ++nact;
         }
 #pragma unroll
-        for (int cc = 0; cc < D; ++cc) rx[k][cc] = t.x[cc];
-        rid[k] = t.id;
+        for (int cc = 0; cc < D; ++cc) rx[k][cc] = t[k].x[cc];
+        rid[k] = t[k].id;
     }
     const uint32_t ndig = 1u << shift;
     staged_write<D, C>(L, rx, rid, w, nact, s.nbuck, 0u, ndig - 1u, ndig, fcur + (c << shift), out, wout);
@@ -550,11 +567,23 @@ __device__ __forceinline__ Rec<D> finish(const StepArgs &s, float (&x)[D], float
     return o;
 }
 
-// LDS slot of the record at global rank r in a bucket starting at lo.
+// LDS slot of the record at global rank r in a bucket starting at lo: one
+// empty slot after every 8, so that the batches the lanes of a wavefront
+// read in the same instruction (each batch's records are contiguous) start
+// in different LDS banks.
 struct Slot {
     uint32_t lo;
-    __device__ __forceinline__ uint32_t operator()(uint32_t r) const { return r - lo; }
+    __device__ __forceinline__ uint32_t operator()(uint32_t r) const
+    {
+        const uint32_t l = r - lo;
+        return l + (l >> 3);
+    }
 };
+// LDS records needed for n sorted records with that spacing
+constexpr uint32_t slot_cap(uint32_t n)
+{
+    return n + n / 8 + 1;
+}
 
 // Member r of the batch of ranks [bs, bs + sz) (any size): its force by
 // direct summation.
@@ -651,11 +680,11 @@ struct FuseOut {
 
 // One workgroup per fine bucket [lo, hi) (SINGLE: the whole system, read
 // from the slot-ordered state, PERM words drawn here).
-//   1. load: records stay in registers; words and ids go to LDS; each record
-//      is counted in its sub-bucket (the next SBITS bits of the word below
-//      the bucket digits)
-//   2. exclusive scan of the sub-bucket counts; member lists per sub-bucket
-//   3. rank = sub-bucket start + members with a smaller (w, id) key
+//   1. load: records stay in registers; each record is counted in its
+//      sub-bucket (the next SBITS bits of the word below the bucket digits)
+//   2. exclusive scan of the sub-bucket counts; the 64-bit keys (w, id) are
+//      listed in LDS in sub-bucket order
+//   3. rank = sub-bucket start + members with a smaller key
 //   4. records written to LDS in sorted order (reusing the ordering bytes)
 //   5. batches inside the bucket, one thread per record (PM > 0: p = PM,
 //      the member loop unrolled).  Records of cut batches go to dst
@@ -677,18 +706,16 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
     constexpr int E = (CAP + TPB - 1) / TPB;
     static_assert(S % TPB == 0, "sub-bucket count must be a multiple of the block");
     static_assert(!FUSED || (!SINGLE && !SORTONLY), "fused output is for the multi-bucket step");
-    constexpr size_t ORDER_BYTES = (size_t)CAP * 10 + (size_t)(S + 1) * 4;
-    constexpr size_t REC_BYTES = (size_t)CAP * sizeof(Rec<D>);
+    constexpr size_t ORDER_BYTES = (size_t)CAP * 8 + (size_t)(S + 1) * 4;
+    constexpr size_t REC_BYTES = (size_t)slot_cap(CAP) * sizeof(Rec<D>);
     __shared__ __align__(16) unsigned char lds[ORDER_BYTES > REC_BYTES ? ORDER_BYTES : REC_BYTES];
     // fused output: two per-digit arrays, the Philox words of the bucket's
     // ranks (WT: at most CAP + 6 of them, in blocks of 4), the staging rounds
     constexpr size_t WT = 4 * ((CAP + 6) / 4 + 1);
     static_assert(8 * LVL_NB + WT * 4 + 64 * (sizeof(Rec<D>) + 4) <= sizeof(lds), "fused staging does not fit");
     __shared__ uint32_t scan_tmp[TPB / 64];
-    uint32_t *wv = reinterpret_cast<uint32_t *>(lds);
-    uint32_t *idv = wv + CAP;
-    uint32_t *cnt = idv + CAP;
-    uint16_t *tmp = reinterpret_cast<uint16_t *>(cnt + S + 1);
+    uint64_t *skey = reinterpret_cast<uint64_t *>(lds);  // [CAP] keys in sub-bucket order
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(skey + CAP);
     Rec<D> *srec = reinterpret_cast<Rec<D> *>(lds);
 
     const uint32_t tid = threadIdx.x;
@@ -707,29 +734,43 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         return;
     }
 
+    // 1. load: every record and word of the thread is requested before any
+    //    is used (indices clamped into the bucket), so their latencies overlap
+    Rec<D> ld[E];
+    uint32_t lw[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t e = min(tid + k * TPB, nb - 1u);
+        ld[k] = src[lo + e];
+        if constexpr (!SINGLE) lw[k] = wsrc[lo + e];
+    }
     // fused: thread c < nb1 gathers the write offset of coarse bucket c for
     // this bucket (its tile's base plus the earlier buckets of the tile) and
-    // this bucket's own count, to check against the counts made here
+    // this bucket's own count, to check against the counts made here; the
+    // loads are all issued at once and used only in the output stage
     uint32_t fgo = 0, fchk = 0;
     if constexpr (FUSED) {
         if (tid < fo.nb1) {
             const uint32_t f = blockIdx.x, f0 = f - f % XG;
+            uint32_t part[XG];
+#pragma unroll
+            for (uint32_t g = 0; g < XG; ++g) part[g] = f0 + g < f ? fo.xrow[(size_t)(f0 + g) * fo.nb1 + tid] : 0u;
             fgo = fo.xbase[(size_t)(f / XG) * fo.nb1 + tid];
-            for (uint32_t g = f0; g < f; ++g) fgo += fo.xrow[(size_t)g * fo.nb1 + tid];
             fchk = fo.xrow[(size_t)f * fo.nb1 + tid];
+#pragma unroll
+            for (uint32_t g = 0; g < XG; ++g) fgo += part[g];
         }
     }
     for (uint32_t i = tid; i <= (uint32_t)S; i += TPB) cnt[i] = 0;
     __syncthreads();
 
-    // 1. load
     float mx[E][D];
-    uint32_t mid[E], msb[E], mpos[E];
+    uint32_t mid[E], mw[E], msb[E], mpos[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
         if (e < nb) {
-            Rec<D> r = src[lo + e];
+            Rec<D> r = ld[k];
             if constexpr (SINGLE) add_pending_noise<D>(s, r.x, r.id);
 #pragma unroll
             for (int c = 0; c < D; ++c) mx[k][c] = r.x[c];
@@ -739,24 +780,21 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
                 const uint4 b4 = philox4x32_10(make_uint4(e >> 2, s.m, STREAM_PERM, s.sys), s.k0, s.k1);
                 w = word_of(b4, e & 3u);
             } else {
-                w = wsrc[lo + e];
+                w = lw[k];
             }
-            wv[e] = w;
-            idv[e] = r.id;
+            mw[k] = w;
             const uint32_t sb = (w * s.nbuck) >> (32 - SBITS);
             msb[k] = sb;
             mpos[k] = atomicAdd(&cnt[sb], 1u);
         }
     }
     __syncthreads();
-    // 2. sub-bucket starts and member lists
-    const uint32_t total = block_exclusive_scan<TPB, S / TPB>(cnt, scan_tmp);
-    if (tid == 0) cnt[S] = total;
-    __syncthreads();
+    // 2. sub-bucket starts (cnt[S] = total) and the keys listed by sub-bucket
+    (void)block_exclusive_scan<TPB, S / TPB, true>(cnt, scan_tmp);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const uint32_t e = tid + k * TPB;
-        if (e < nb) tmp[cnt[msb[k]] + mpos[k]] = (uint16_t)e;
+        if (e < nb) skey[cnt[msb[k]] + mpos[k]] = ((uint64_t)mw[k] << 32) | mid[k];
     }
     __syncthreads();
     // 3. exact ranks
@@ -766,15 +804,10 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
         const uint32_t e = tid + k * TPB;
         mrank[k] = 0;
         if (e < nb) {
-            const uint32_t w = wv[e];
-            const uint32_t id = mid[k];
+            const uint64_t key = ((uint64_t)mw[k] << 32) | mid[k];
             const uint32_t b0 = cnt[msb[k]], b1 = cnt[msb[k] + 1];
             uint32_t rank = b0;
-            for (uint32_t j = b0; j < b1; ++j) {
-                const uint32_t t = tmp[j];
-                const uint32_t wt = wv[t];
-                rank += (wt < w || (wt == w && idv[t] < id)) ? 1u : 0u;
-            }
+            for (uint32_t j = b0; j < b1; ++j) rank += skey[j] < key ? 1u : 0u;
             mrank[k] = rank;
         }
     }
@@ -831,7 +864,7 @@ __global__ __launch_bounds__(TPB) void k_sort_step(StepArgs s, const Rec<D> *src
                 if (r >= ins_lo && r < ins_hi) {
                     u[k] = batch_member<D, KERN, PM>(s, srec, pad, r, nullptr);
                 } else {
-                    u[k] = srec[l];
+                    u[k] = srec[pad(r)];
                     dst[r] = u[k];
                 }
             }
