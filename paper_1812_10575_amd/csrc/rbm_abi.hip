@@ -36,6 +36,11 @@ struct rbm_ctx {
     hipEvent_t *ev;   // tmax * (RBM_NPHASES + 1) events
     int32_t tmax;     // steps the pool can record
     int32_t trec;     // steps recorded so far
+    // fused runs: the key passes of the next group of steps run on a second
+    // stream (default priority) while the current group's steps run
+    hipStream_t ks;
+    hipEvent_t ev_go, ev_keys;
+    bool side;
 };
 
 namespace {
@@ -130,12 +135,16 @@ Plan make_plan(const rbm_params *prm)
         // at most RBM_MAX_FINE fine buckets (the one-workgroup scan of the
         // bucket totals) and so at most RBM_MAX_FINE / 2^shift coarse ones
         const uint32_t target = std::min<uint32_t>((pl.n + RBM_BUCKET_MEAN - 1) / RBM_BUCKET_MEAN, RBM_MAX_FINE);
-        const uint32_t per = 1u << RBM_SPLIT_SHIFT;
+        // 2^shift fine buckets per coarse one: RBM_SPLIT_SHIFT, or more when
+        // the coarse buckets would not fit the digit arrays
+        uint32_t shift = RBM_SPLIT_SHIFT;
+        while ((target >> shift) >= RBM_MAX_COARSE) ++shift;
+        const uint32_t per = 1u << shift;
         if (target <= per) {
             pl.shift = 0;
             pl.nb1 = pl.nbuck = target;
         } else {
-            pl.shift = RBM_SPLIT_SHIFT;
+            pl.shift = shift;
             pl.nb1 = (target + per - 1) / per;
             pl.nbuck = pl.nb1 * per;
             // chunks per coarse bucket: room for the mean plus 16 standard deviations
@@ -342,8 +351,26 @@ rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_
     ctx->plan = pl;
     ctx->ws = d_ws;
     ctx->m = step0;
+    if (pl.fuse) {
+        // the stream and events of the overlapped key passes (no device memory)
+        hipError_t e = hipStreamCreateWithFlags(&ctx->ks, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_go, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_keys, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (ctx->ev_go) (void)hipEventDestroy(ctx->ev_go);
+            if (ctx->ks) (void)hipStreamDestroy(ctx->ks);
+            free(ctx);
+            return hip_fail(e, "rbm_init stream");
+        }
+        ctx->side = true;
+    }
     hipError_t e = rbm::launch_init(pl, prm->d, d_x0, d_slots, d_ws, (hipStream_t)stream);
     if (e != hipSuccess) {
+        if (ctx->side) {
+            (void)hipEventDestroy(ctx->ev_go);
+            (void)hipEventDestroy(ctx->ev_keys);
+            (void)hipStreamDestroy(ctx->ks);
+        }
         free(ctx);
         return hip_fail(e, "rbm_init launch");
     }
@@ -355,6 +382,65 @@ rbm_status rbm_init(const rbm_params *prm, const float *d_x0, const uint32_t *d_
 rbm_status rbm_step(rbm_ctx *ctx, void *stream)
 {
     return rbm_run(ctx, 1, stream);
+}
+
+// A fused run whose key passes overlap the steps.  Groups of steps share key
+// passes as in rbm_run below (banks of key sets alternating); the first
+// group is small (its passes are on the critical path), the later ones hold
+// up to kb steps.  At the start of group g (all steps of group g - 1
+// enqueued before it, so its bank is free) the side stream makes the key
+// passes of group g + 1 in that bank, with the transition from group g's last
+// step into group g + 1's first; the main stream waits for them before group
+// g's last step, whose sort kernel writes the coarse buckets of group g + 1.
+// The same kernels on the same data in the same order per stream: the bits
+// are those of the serial order.
+static rbm_status run_overlapped(rbm_ctx *ctx, int64_t nsteps, hipStream_t hs)
+{
+    const Plan &pl = ctx->plan;
+    void *state = (char *)ctx->ws + pl.off_state;
+    constexpr int64_t FIRST = 2;
+    int64_t k = 0;
+    int64_t gsize = std::min<int64_t>(FIRST, nsteps);
+    uint32_t bank = 0;
+    {
+        const StepArgs s0 = make_args(&ctx->prm, pl, (uint32_t)ctx->m, ctx->pending);
+        hipError_t e = rbm::launch_keys(pl, s0, (uint32_t)gsize, ctx->ws, hs, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "rbm_run key launch");
+    }
+    bool prev_out = false;
+    while (k < nsteps) {
+        const int64_t rest = nsteps - k - gsize;  // steps after this group
+        const int64_t next = std::min<int64_t>(pl.kb, rest);
+        if (next > 0) {
+            hipError_t e = hipEventRecord(ctx->ev_go, hs);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ctx->ks, ctx->ev_go, 0);
+            if (e != hipSuccess) return hip_fail(e, "rbm_run side stream");
+            const StepArgs sn = make_args(&ctx->prm, pl, (uint32_t)(ctx->m + gsize), false);
+            e = rbm::launch_keys(pl, sn, (uint32_t)next, ctx->ws, ctx->ks, nullptr, (bank ^ 1u) * pl.kb,
+                                 bank * pl.kb + (uint32_t)gsize - 1u);
+            if (e == hipSuccess) e = hipEventRecord(ctx->ev_keys, ctx->ks);
+            if (e != hipSuccess) return hip_fail(e, "rbm_run key launch");
+        }
+        for (int64_t i = 0; i < gsize; ++i) {
+            const StepArgs s = make_args(&ctx->prm, pl, (uint32_t)ctx->m, ctx->pending);
+            const bool out = k + i + 1 < nsteps;
+            if (out && i + 1 == gsize) {
+                hipError_t e = hipStreamWaitEvent(hs, ctx->ev_keys, 0);
+                if (e != hipSuccess) return hip_fail(e, "rbm_run side stream");
+            }
+            const uint32_t fuse = (prev_out ? 1u : 0u) | (out ? 2u : 0u);
+            hipError_t e = rbm::launch_step(pl, s, pl.d, pl.kernel, ctx->ws, hs, state, nullptr, nullptr,
+                                            bank * pl.kb + (uint32_t)i, true, fuse);
+            if (e != hipSuccess) return hip_fail(e, "rbm_step launch");
+            prev_out = out;
+            ctx->m += 1;
+            ctx->pending = s.ssd != 0.0f;
+        }
+        k += gsize;
+        gsize = next;
+        bank ^= 1u;
+    }
+    return RBM_OK;
 }
 
 rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
@@ -373,6 +459,7 @@ rbm_status rbm_run(rbm_ctx *ctx, int64_t nsteps, void *stream)
     // group, and from a group's last step into the next group (made with that
     // group's key passes, before the step).  Only the call's first step runs
     // the coarse scatter and its last leaves the state in slot order.
+    if (ctx->side && ctx->tmax == 0 && nsteps > 1) return run_overlapped(ctx, nsteps, hs);
     uint32_t set = 0, group = 0, bank = 0, next_group = 0;
     bool prev_out = false;
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -548,6 +635,13 @@ rbm_status rbm_destroy(rbm_ctx *ctx)
 {
     if (!ctx) return RBM_OK;
     if (ctx->ev) release_events(ctx);
+    if (ctx->side) {
+        // work of this context still queued on the side stream ends first
+        (void)hipStreamSynchronize(ctx->ks);
+        (void)hipEventDestroy(ctx->ev_go);
+        (void)hipEventDestroy(ctx->ev_keys);
+        (void)hipStreamDestroy(ctx->ks);
+    }
     free(ctx);
     return RBM_OK;
 }

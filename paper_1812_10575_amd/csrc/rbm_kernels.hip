@@ -481,7 +481,7 @@ __global__ __launch_bounds__(SCATTER_TPB) void k_scatter_coarse(StepArgs s, uint
 // Split: chunk j of coarse bucket c (workgroup c * jmax + j; C::P x C::TPB
 // records) into the 2^shift fine buckets of c, adding the pending noise of s.
 template <int D, class C>
-__global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax,
+__global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift, uint32_t jmax, uint32_t nb1,
                                                    const uint32_t *__restrict__ cstart,
                                                    const Rec<D> *__restrict__ in,
                                                    const uint32_t *__restrict__ win,
@@ -493,7 +493,16 @@ __global__ __launch_bounds__(SPLIT_TPB) void k_split(StepArgs s, uint32_t shift,
     static_assert(C::TPB == SPLIT_TPB, "one split block size");
     constexpr uint32_t CH = (uint32_t)(C::P * C::TPB);
     __shared__ StageLds<D, C> L;
+#ifdef RBM_SPLIT_XCD
+    // every chunk of coarse bucket c runs on XCD c mod 8 (workgroups are
+    // dealt to the 8 XCDs in turn), so the lines that neighbouring runs of a
+    // fine bucket share meet in one L2
+    const uint32_t xcd = blockIdx.x & 7u, k = blockIdx.x >> 3;
+    const uint32_t c = xcd + 8u * (k / jmax), j = k % jmax;
+    if (c >= nb1) return;
+#else
     const uint32_t c = blockIdx.x / jmax, j = blockIdx.x % jmax;
+#endif
     const uint32_t c0 = cstart[c], c1 = cstart[c + 1];
     // the jmax chunks must cover the coarse bucket (mean + 16 sd of room)
     if (j == 0 && threadIdx.x == 0 && c1 - c0 > jmax * CH) atomicOr(flags, 1u);
@@ -534,12 +543,17 @@ template <int D>
 void launch_split(const Plan &pl, hipStream_t st, const StepArgs &s, const uint32_t *cstart, const Rec<D> *in,
                   const uint32_t *win, uint32_t *fcur, Rec<D> *out, uint32_t *wout, uint32_t *flags)
 {
+#ifdef RBM_SPLIT_XCD
+    const uint32_t grid = 8u * ((pl.nb1 + 7u) / 8u) * pl.jmax;
+#else
+    const uint32_t grid = pl.nb1 * pl.jmax;
+#endif
     if (pl.chunk == (uint32_t)RBM_CHUNK_SMALL)
-        hipLaunchKernelGGL((k_split<D, LvlSplitSmall>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
-                           pl.jmax, cstart, in, win, fcur, out, wout, flags);
+        hipLaunchKernelGGL((k_split<D, LvlSplitSmall>), dim3(grid), dim3(SPLIT_TPB), 0, st, s, pl.shift,
+                           pl.jmax, pl.nb1, cstart, in, win, fcur, out, wout, flags);
     else
-        hipLaunchKernelGGL((k_split<D, LvlSplit>), dim3(pl.nb1 * pl.jmax), dim3(SPLIT_TPB), 0, st, s, pl.shift,
-                           pl.jmax, cstart, in, win, fcur, out, wout, flags);
+        hipLaunchKernelGGL((k_split<D, LvlSplit>), dim3(grid), dim3(SPLIT_TPB), 0, st, s, pl.shift,
+                           pl.jmax, pl.nb1, cstart, in, win, fcur, out, wout, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,10 +649,30 @@ __device__ __forceinline__ Rec<D> member_fixed(const StepArgs &s, const Rec<D> *
             return finish<D>(s, y, f, me.id, fout);
         }
     }
+    // every member is read before any pair is evaluated (the reads are in
+    // flight together); the own term is left out by a select, so the sum is
+    // the same additions in the same order as skipping it
+    constexpr int DK = kdim<D, KERN>();
+    float xm[PM][DK];
 #pragma unroll
     for (int j = 0; j < PM; ++j) {
-        const uint32_t rj = bs + (uint32_t)j;
-        if (rj != r) add_pair<D, KERN>(xi, srec[pad(rj)].x, s.a, f);
+        const Rec<D> o = srec[pad(bs + (uint32_t)j)];
+#pragma unroll
+        for (int c = 0; c < DK; ++c) xm[j][c] = o.x[c];
+    }
+#pragma unroll
+    for (int j = 0; j < PM; ++j) {
+        float dx[DK];
+        float r2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < DK; ++c) {
+            dx[c] = xi[c] - xm[j][c];
+            r2 = fmaf(dx[c], dx[c], r2);
+        }
+        const float sc = pair_scale<KERN>(r2, s.a);
+        const bool other = bs + (uint32_t)j != r;
+#pragma unroll
+        for (int c = 0; c < DK; ++c) f[c] = other ? fmaf(sc, dx[c], f[c]) : f[c];
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) f[c] *= s.inv_p1;
@@ -1204,7 +1238,7 @@ constexpr int SINGLE_SBITS = 11;
 constexpr int SORT_TPB = 512;
 constexpr int SORT_CAP = RBM_SORT_CAP;
 constexpr int SORT_SBITS = 11;
-static_assert((RBM_MAX_FINE >> RBM_SPLIT_SHIFT) <= LVL_NB && (1 << RBM_SPLIT_SHIFT) <= LVL_NB,
+static_assert((RBM_MAX_FINE >> 7) <= LVL_NB && (1 << RBM_SPLIT_SHIFT) <= LVL_NB && RBM_SPLIT_SHIFT <= 7,
               "digits beyond the staging arrays");
 constexpr int DIRECT_TPB = 256;
 

@@ -19,7 +19,9 @@
 // fused sort kernel fits 64 VGPRs (eight waves per SIMD).  Buckets this large
 // keep the coarse buckets few (78 at N = 2^24), so the runs that a scatter
 // writes per coarse bucket are long.
+#ifndef RBM_BUCKET_MEAN
 #define RBM_BUCKET_MEAN 1700
+#endif
 #define RBM_SORT_CAP 2048
 #define RBM_KEY_SETS 16
 #define RBM_MAX_FINE 32768
@@ -32,9 +34,15 @@
 #define RBM_SCATTER_TPB 512
 #define RBM_SCATTER_P 16
 #define RBM_LVL_RPT 4
+#ifndef RBM_SPLIT_TPB
 #define RBM_SPLIT_TPB 1024
+#endif
+#ifndef RBM_SPLIT_P
 #define RBM_SPLIT_P 12
+#endif
+#ifndef RBM_SPLIT_RPT
 #define RBM_SPLIT_RPT 6
+#endif
 #define RBM_TILE (RBM_SCATTER_P * RBM_SCATTER_TPB)
 #define RBM_CHUNK (RBM_SPLIT_P * RBM_SPLIT_TPB)
 // A plan with fewer than RBM_SPLIT_FEW split chunks of RBM_CHUNK records
@@ -43,7 +51,9 @@
 #define RBM_SPLIT_SMALL_P 4
 #define RBM_CHUNK_SMALL (RBM_SPLIT_SMALL_P * RBM_SPLIT_TPB)
 #define RBM_SPLIT_FEW 512
+#ifndef RBM_SPLIT_SHIFT
 #define RBM_SPLIT_SHIFT 7
+#endif
 // Coarse buckets (digits of the scatter level) at most: the per-digit arrays
 // of the staging levels and of the fused sort output, and the one-byte
 // coarse digits of the key passes.
