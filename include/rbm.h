@@ -371,8 +371,13 @@ const char *rbm_last_error(void);
 #define RBM_RBMR_MAX_WINDOW (1u << 22)
 #define RBM_RBMR_MAX_ROUNDS 255
 
-/* Bytes of device workspace rbmr_run needs: 16 N (32 N for d = 3) +
- * 8 window + 4 (rounds + 1), each part rounded up to 256. */
+/* Bytes of device workspace rbmr_run needs: 16 N (particle records) +
+ * 16 window p (the window's member entries, sorted by particle, and their
+ * successors) + 2 x 1024 (ceil(window / 256) + 512) (two round queues of
+ * 256 segments) + 4 B (G + 2) (the schedule sort's counts and starts: B <=
+ * 8192 buckets of consecutive particles, G = ceil(window / max(4096,
+ * ceil(window / 256))) <= 256 counting workgroups) + 1024 (rounds + 2)
+ * (queue lengths), each part rounded up to 256. */
 rbm_status rbmr_workspace_size(const rbm_params *prm, int64_t window, int32_t rounds, size_t *bytes);
 
 /* Iterations k0 .. k0 + niter - 1 on d_x ([N][d] FP32 positions by particle
@@ -394,8 +399,8 @@ rbm_status rbmr_run(const rbm_params *prm, float *d_x, int64_t k0, int64_t niter
  * call allocates nothing (no hipMalloc, no allocating library routine).
  * Same arguments, limits, results (bit for bit) and errors as rbmr_run;
  * RBM_ERR_WORKSPACE when rbmr_workspace_size(prm, window, rounds) exceeds
- * RBM_NOALLOC_SCRATCH_BYTES (e.g. d <= 2 fits N up to 2^21 with the default
- * window, d = 3 up to 2^20).  Every call on one GPU shares that GPU's
+ * RBM_NOALLOC_SCRATCH_BYTES (with the default window N/p, about 36 N bytes
+ * for p = 2: N up to 2^20 fits, 2^21 does not).  Every call on one GPU shares that GPU's
  * buffer: calls that overlap on one GPU (on different streams, or from
  * different threads) race and give undefined results; calls in one stream
  * order are safe.  Nothing of a call's buffer contents is carried into the

@@ -1020,7 +1020,8 @@ rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_
 // ---------------------------------------------------------------------------
 // RBM-r
 // ---------------------------------------------------------------------------
-static_assert(RBMR_MAX_P == RBM_RBMR_MAX_P && RBMR_MAX_WINDOW == RBM_RBMR_MAX_WINDOW,
+static_assert(RBMR_MAX_P == RBM_RBMR_MAX_P && RBMR_MAX_WINDOW == RBM_RBMR_MAX_WINDOW &&
+                  RBMR_MAX_ROUNDS == RBM_RBMR_MAX_ROUNDS && (uint64_t)RBMR_MAX_NBK * RBMR_MAX_PB >= RBM_MAX_N,
               "RBM-r limits of the header and the kernels differ");
 
 static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t rounds, rbm::RbmrLayout *lay)
@@ -1053,7 +1054,7 @@ static rbm_status rbmr_plan(const rbm_params *prm, int64_t window, int32_t round
     }
     if (rounds < 1 || rounds > RBM_RBMR_MAX_ROUNDS)
         return fail(RBM_ERR_INVALID, "rounds %d not in 1..%d", rounds, RBM_RBMR_MAX_ROUNDS);
-    *lay = rbm::rbmr_layout((uint32_t)prm->n, (uint32_t)prm->d, (uint32_t)window, (uint32_t)rounds);
+    *lay = rbm::rbmr_layout((uint32_t)prm->n, (uint32_t)prm->p, (uint32_t)window, (uint32_t)rounds);
     return RBM_OK;
 }
 

@@ -80,7 +80,7 @@ def test_noalloc_three_dimensions_and_window():
 
 
 def test_noalloc_rejects_a_run_above_the_buffer():
-    # 1-D, N = 2^22, p = 2 needs 16 N + 8 N/2 bytes = 80 MiB > 64 MiB
+    # 1-D, N = 2^22, p = 2 needs about 16 N + 16 N + 8 N/2 bytes = 144 MiB > 64 MiB
     w = rbm_inputs.params_of("dysonrbmr1d-n2^20-p2", n=1 << 22, sigma=1.0 / math.sqrt(1 << 22))
     assert rbm.rbmr_workspace_size(gp(w)) > rbm.NOALLOC_SCRATCH_BYTES
     x = torch.zeros((w["n"], 1), dtype=torch.float32, device="cuda")
