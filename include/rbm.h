@@ -206,8 +206,10 @@ rbm_status rbm_destroy(rbm_ctx *ctx);
  * z sigma(2 sqrt(2/pi) z (1 + 0.044715 z^2)), after the hidden layers;
  * outputs read as [component 2][rank 16]) evaluated with BF16 matrix
  * instructions (FP32 accumulation).  A step evaluates c once for every
- * particle (for S, kept in the workspace) and a once; the workspace of a
- * cv = 1 context adds 140 bytes per particle.  Parameters of one net, FP32, in order:
+ * particle and rounds it to BF16 (to nearest even): S sums those rounded
+ * values and the batch term uses them, kept in the workspace; a is evaluated
+ * once and stays FP32.  The workspace of a cv = 1 context adds 76 bytes per
+ * particle.  Parameters of one net, FP32, in order:
  * W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32]; a then c.
  * rbm_init initialises them (cv_init with the context's seed). */
 
@@ -306,7 +308,8 @@ rbm_status ensemble_workspace_size(const rbm_ensemble *e, const int64_t *h_n, si
  * d_x: packed FP32 positions [sum N_s][d], system by system, each by
  * particle id; read at the start and overwritten with the final positions.
  * tile: launch shape (NULL: defaults).  graph != 0: the launch is recorded
- * into a hipGraph on a private stream and replayed once.  Waits for
+ * into a hipGraph on a private stream and replayed once (a graph of one
+ * kernel node: the same work and time as the direct launch, graph = 0).  Waits for
  * completion and returns RBM_ERR_DEVICE if a device-side check failed. */
 rbm_status ensemble_run(const rbm_ensemble *e, const int64_t *h_n, const uint64_t *h_seed,
                         float *d_x, int64_t step0, int64_t nsteps,

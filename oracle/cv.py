@@ -27,7 +27,10 @@ W1[64][2], b1[64], W2[64][64], b2[64], W3[32][64], b3[32] (6432 values).
 `use_bf16=True` rounds (to nearest even) exactly the operands the GPU feeds
 to its BF16 matrix instructions: W2, W3 and the hidden activations h1, h2 in
 the forward pass; dO, delta2, h1, h2 and the weights in every product of the
-backward pass (the bias and first-layer gradients stay unrounded).
+backward pass (the bias and first-layer gradients stay unrounded).  In the
+force (cv_forces, cv_forces_ids, cv_step) it also rounds the output of c to
+BF16, as the GPU stores it: S sums the rounded values and the batch term uses
+them, so the force stays exactly unbiased; a stays unrounded.
 """
 from __future__ import annotations
 
@@ -103,6 +106,13 @@ def forward(theta, x, use_bf16=False):
 def features(theta, x, use_bf16=False):
     """Network output [n][2][16]."""
     return forward(theta, x, use_bf16)[4].reshape(-1, DIM, RANK)
+
+
+def c_features(theta_c, x, use_bf16=False):
+    """Output of the c network as the force uses it: [n][2][16], rounded to
+    BF16 with use_bf16."""
+    c = features(theta_c, x, use_bf16)
+    return bf16(c) if use_bf16 else c
 
 
 def pair_kernel_gauss(dx):
@@ -201,7 +211,7 @@ def cv_forces(theta_a, theta_c, x, perm, p, kfun=pair_kernel_gauss, use_bf16=Fal
     perm = np.asarray(perm, np.int64)
     n = x.shape[0]
     a = features(theta_a, x, use_bf16)     # [N][2][16]
-    c = features(theta_c, x, use_bf16)
+    c = c_features(theta_c, x, use_bf16)
     S = c.sum(axis=0)                       # exact sum (FP64)
     f = np.einsum("ikr,ikr->ik", a, S[None] - c) / (n - 1)
     nb = n // p
@@ -230,7 +240,7 @@ def cv_forces_ids(theta_a, theta_c, x, perm, p, ids, kfun=pair_kernel_gauss, use
     n = x.shape[0]
     S = np.zeros((DIM, RANK))
     for s0 in range(0, n, chunk):
-        S += features(theta_c, x[s0:s0 + chunk], use_bf16).sum(axis=0)
+        S += c_features(theta_c, x[s0:s0 + chunk], use_bf16).sum(axis=0)
     rank = np.empty(n, np.int64)
     rank[perm] = np.arange(n)
     nb = n // p
@@ -240,8 +250,8 @@ def cv_forces_ids(theta_a, theta_c, x, perm, p, ids, kfun=pair_kernel_gauss, use
         bs = q * p
         mates = perm[bs:(n if q == nb - 1 else bs + p)]
         a = features(theta_a, x[[i]], use_bf16)[0]
-        c = features(theta_c, x[mates], use_bf16)
-        ci = features(theta_c, x[[i]], use_bf16)[0]
+        c = c_features(theta_c, x[mates], use_bf16)
+        ci = c_features(theta_c, x[[i]], use_bf16)[0]
         f = np.einsum("kr,kr->k", a, S - ci) / (n - 1)
         res = np.zeros(DIM)
         for jj, j in enumerate(mates):

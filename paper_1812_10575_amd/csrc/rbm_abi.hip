@@ -208,7 +208,7 @@ Plan make_plan(const rbm_params *prm)
     pl.cv = prm->cv;
     if (pl.cv) {
         pl.off_sorted = take(recs);
-        pl.off_cvc = take((size_t)pl.n * CV_NO * 4);
+        pl.off_cvc = take((size_t)pl.n * CV_NO * 2);
         pl.off_cvmaster = take((size_t)2 * CV_NP * 4);
         pl.off_cvam = take((size_t)2 * CV_NP * 4);
         pl.off_cvav = take((size_t)2 * CV_NP * 4);

@@ -40,14 +40,19 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16 *p)
 
 // GELU in its tanh form, 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
 // written as z sigma(v) with v = 2 sqrt(2/pi) z (1 + 0.044715 z^2): one
-// exponential and one reciprocal on the VALU.
+// base-2 exponential and one reciprocal on the VALU.  The constants of v and
+// of the change of base are folded, so that sigma takes two multiplies, one
+// FMA and one add besides the two transcendental instructions:
+// exp(-v) = 2^(z (A z^2 + B)), B = -2 sqrt(2/pi) log2(e), A = 0.044715 B.
 constexpr float GELU_K = 1.5957691216057308f;  // 2 sqrt(2/pi)
 constexpr float GELU_C = 0.044715f;
+constexpr float GELU_B = -2.3022082f;          // -2 sqrt(2/pi) / ln 2
+constexpr float GELU_A = -0.10294324f;         // 0.044715 GELU_B
 
 __device__ __forceinline__ float gelu_sig(float z)
 {
-    const float v = GELU_K * z * fmaf(GELU_C, z * z, 1.0f);
-    return __builtin_amdgcn_rcpf(1.0f + __expf(-v));
+    const float w = z * fmaf(GELU_A, z * z, GELU_B);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(w));
 }
 
 __device__ __forceinline__ float gelu(float z)
@@ -308,9 +313,12 @@ __device__ __forceinline__ void fwd_tile(const NetLds &N, float x0, float x1, __
 }
 
 // Partial sums of c(X_j) over the records (pending noise of s added, if
-// any): part[wg][32] in FP64, and c itself to cout[j][32] (FP32) when cout is
-// not null.  Workgroup wg takes tiles of 256 records wg, wg + G, ...; each
-// lane sums its samples in tile order, then the lanes and waves of the
+// any): part[wg][32] in FP64, and c itself to cout[j][32] when cout is not
+// null.  c is rounded to BF16 where it is produced: the sums add the
+// rounded values, so that S and the c that phase B reads are the same
+// numbers (the residual force stays exactly unbiased), and phase B reads
+// half the bytes.  Workgroup wg takes tiles of 256 records wg, wg + G, ...;
+// each lane sums its samples in tile order, then the lanes and waves of the
 // workgroup are added in a fixed order.
 struct SumLds {
     NetLds net;
@@ -322,7 +330,7 @@ struct SumLds {
 __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restrict__ state,
                                               const float *__restrict__ master,
                                               const __bf16 *__restrict__ wb,
-                                              double *__restrict__ part, float *__restrict__ cout)
+                                              double *__restrict__ part, __bf16 *__restrict__ cout)
 {
     __shared__ SumLds L;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
@@ -351,11 +359,12 @@ __global__ __launch_bounds__(256) void k_csum(StepArgs s, const Rec<2> *__restri
             for (int i = 0; i < 4; ++i) {
                 const uint32_t r = base + m + 4 * g + i;
                 if (r < s.n) {
-                    acc[0] += (double)out[0][i];
-                    acc[1] += (double)out[1][i];
+                    const __bf16 c0 = (__bf16)out[0][i], c1 = (__bf16)out[1][i];
+                    acc[0] += (double)(float)c0;
+                    acc[1] += (double)(float)c1;
                     if (cout) {
-                        cout[(size_t)r * CV_NO + col] = out[0][i];
-                        cout[(size_t)r * CV_NO + 16 + col] = out[1][i];
+                        cout[(size_t)r * CV_NO + col] = c0;
+                        cout[(size_t)r * CV_NO + 16 + col] = c1;
                     }
                 }
             }
@@ -404,15 +413,22 @@ struct BatchLds {
     float X[CV_MAXR][2];
     uint32_t id[CV_MAXR];
     float A[CV_MAXR][CV_NO + 1];  // padded rows: one record per lane hits distinct banks
-    float C[CV_MAXR][CV_NO + 1];
+    uint32_t C[CV_MAXR][CV_NO / 2 + 1];  // BF16 pairs (element 2w in the low half of word w), padded
     __bf16 H2[4][16][WP];
     float sn[CV_NO];  // S / (N - 1)
 };
 
+// Element e of a BF16 row stored as pairs in 32-bit words.
+__device__ __forceinline__ float bf16_at(const uint32_t *row, int e)
+{
+    const uint32_t w = row[e >> 1];
+    return __uint_as_float((e & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+
 template <int KERN>
-__global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint32_t ntiles,
+__global__ __launch_bounds__(256, 3) void k_cv_batch(StepArgs s, uint32_t qb, uint32_t ntiles,
                                                   const Rec<2> *__restrict__ sorted,
-                                                  const float *__restrict__ cin,
+                                                  const __bf16 *__restrict__ cin,
                                                   const float *__restrict__ master,
                                                   const __bf16 *__restrict__ wb,
                                                   const double *__restrict__ S,
@@ -438,11 +454,14 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
         __syncthreads();              // the previous tile is done with the LDS
         // c of the tile's records (computed with S by k_csum): loaded now,
         // stored to LDS once a is computed, so the loads overlap that work
-        float cr[CV_MAXR * CV_NO / 256];
+        // (16 B per load: elements 8 tid + 2048 k .. + 7, whole or absent
+        // since a row holds 32)
+        uint4 cr[CV_MAXR * CV_NO / 2048];
 #pragma unroll
-        for (int k = 0; k < CV_MAXR * CV_NO / 256; ++k) {
-            const uint32_t e = tid + 256 * k;
-            cr[k] = e < nr * CV_NO ? cin[(size_t)r0 * CV_NO + e] : 0.0f;
+        for (int k = 0; k < CV_MAXR * CV_NO / 2048; ++k) {
+            const uint32_t e = 8 * tid + 2048 * k;
+            cr[k] = e < nr * CV_NO ? *reinterpret_cast<const uint4 *>(cin + (size_t)r0 * CV_NO + e)
+                                   : make_uint4(0u, 0u, 0u, 0u);
         }
         if (tid < CV_MAXR) {
             float xy[2] = {0.0f, 0.0f};
@@ -470,9 +489,13 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
                 for (int i = 0; i < 4; ++i) L.A[m + 4 * g + i][16 * t + col] = out[t][i];
         }
 #pragma unroll
-        for (int k = 0; k < CV_MAXR * CV_NO / 256; ++k) {
-            const uint32_t e = tid + 256 * k;
-            L.C[e / CV_NO][e % CV_NO] = cr[k];
+        for (int k = 0; k < CV_MAXR * CV_NO / 2048; ++k) {
+            const uint32_t e = 8 * tid + 2048 * k;
+            uint32_t *w = &L.C[e / CV_NO][(e % CV_NO) / 2];
+            w[0] = cr[k].x;
+            w[1] = cr[k].y;
+            w[2] = cr[k].z;
+            w[3] = cr[k].w;
         }
         __syncthreads();
         // forces, one thread per record
@@ -487,7 +510,7 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
                 float acc = 0.0f;
 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr)
-                    acc = fmaf(a[16 * k + rr], L.sn[16 * k + rr] - L.C[l][16 * k + rr] * inv_n1, acc);
+                    acc = fmaf(a[16 * k + rr], L.sn[16 * k + rr] - bf16_at(L.C[l], 16 * k + rr) * inv_n1, acc);
                 f[k] = acc;
             }
             const float xi[2] = {L.X[l][0], L.X[l][1]};
@@ -501,7 +524,7 @@ __global__ __launch_bounds__(256) void k_cv_batch(StepArgs s, uint32_t qb, uint3
                 for (int k = 0; k < 2; ++k) {
                     float dot = 0.0f;
 #pragma unroll
-                    for (int rr = 0; rr < 16; ++rr) dot = fmaf(a[16 * k + rr], L.C[lj][16 * k + rr], dot);
+                    for (int rr = 0; rr < 16; ++rr) dot = fmaf(a[16 * k + rr], bf16_at(L.C[lj], 16 * k + rr), dot);
                     res[k] += kv[k] - dot;
                 }
             }
@@ -846,7 +869,7 @@ hipError_t cv_launch_features(const float *master, const __bf16 *wb, const float
 }
 
 hipError_t cv_launch_csum(const StepArgs &s, const void *state, const float *master,
-                          const __bf16 *wb, double *part, double *S, float *cout, hipStream_t st)
+                          const __bf16 *wb, double *part, double *S, __bf16 *cout, hipStream_t st)
 {
     const uint32_t g = min((s.n + 255) / 256, (uint32_t)CV_SUM_WG);
     hipLaunchKernelGGL(cvk::k_csum, dim3(g), dim3(256), 0, st, s, (const Rec<2> *)state, master, wb,
@@ -855,7 +878,7 @@ hipError_t cv_launch_csum(const StepArgs &s, const void *state, const float *mas
     return hipGetLastError();
 }
 
-hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const float *c,
+hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const __bf16 *c,
                            const float *master, const __bf16 *wb, const double *S, void *dst, float *fout,
                            hipStream_t st)
 {

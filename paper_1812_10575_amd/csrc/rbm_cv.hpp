@@ -33,13 +33,13 @@ hipError_t cv_launch_glorot(float *master, uint64_t seed, hipStream_t st);
 hipError_t cv_launch_prep(const float *master, __bf16 *wb, hipStream_t st);
 hipError_t cv_launch_features(const float *master, const __bf16 *wb, const float *x, uint32_t n,
                               float *a, float *c, hipStream_t st);
-// S = sum of c over the n records of `state` (pending noise of s added);
-// cout (may be null): c of every record, [n][32] FP32.
+// S = sum of c over the n records of `state` (pending noise of s added), of
+// c rounded to BF16; cout (may be null): those rounded c, [n][32] BF16.
 hipError_t cv_launch_csum(const StepArgs &s, const void *state, const float *master,
-                          const __bf16 *wb, double *part, double *S, float *cout, hipStream_t st);
+                          const __bf16 *wb, double *part, double *S, __bf16 *cout, hipStream_t st);
 // Batch forces over key-ordered records `sorted`, with c of the same records
-// in c ([n][32]) and S.
-hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const float *c,
+// in c ([n][32] BF16) and S.
+hipError_t cv_launch_batch(const StepArgs &s, int kernel, const void *sorted, const __bf16 *c,
                            const float *master, const __bf16 *wb, const double *S, void *dst, float *fout,
                            hipStream_t st);
 hipError_t cv_launch_grad(uint32_t npairs, float ka, const float *xs, const float *ys,

@@ -1369,11 +1369,11 @@ hipError_t step_cv(const Plan &pl, const StepArgs &s, void *ws, hipStream_t st, 
                            FuseOut<2>{});
     }
     // phase A over the key-ordered records (their noise is in): c of every
-    // particle, kept for phase B, and S; timed with the batch phase
+    // particle (BF16), kept for phase B, and S; timed with the batch phase
     mark(ev, 6, st);
     StepArgs sa = s;
     sa.pssd = 0.0f;
-    float *cbuf = at<float>(ws, pl.off_cvc);
+    __bf16 *cbuf = at<__bf16>(ws, pl.off_cvc);
     e = cv_launch_csum(sa, sorted, master, wb, at<double>(ws, pl.off_cvspart), S, cbuf, st);
     if (e != hipSuccess) return e;
     e = cv_launch_batch(s, K_GAUSS, sorted, cbuf, master, wb, S, dst_state, fout, st);

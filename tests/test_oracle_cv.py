@@ -97,19 +97,28 @@ def _direct_gauss(x):
     return f
 
 
+@pytest.mark.parametrize("use_bf16", [False, True])
 @pytest.mark.parametrize("n,p", [(6, 2), (7, 3), (8, 4)])
-def test_cv_force_is_unbiased_for_any_weights(thetas, n, p):
+def test_cv_force_is_unbiased_for_any_weights(thetas, n, p, use_bf16):
     """Over every division, the mean control-variate force is the direct
     force (Lemma 3.1 applied to the residual kernel), and for p | N its
-    variance is (1/(p-1) - 1/(N-1)) Lambda_i[K_res]."""
+    variance is (1/(p-1) - 1/(N-1)) Lambda_i[K_res].  With use_bf16 the
+    networks run on BF16 operands and c is rounded to BF16: the residual
+    kernel is then K - a . bf16(c), and the force stays exactly unbiased only
+    if S and the batch term take the same rounded c."""
     ta, tc = thetas
     x = rbm_inputs.normal(n, 2, seed=n + 40).astype(np.float64)
-    fs = np.array([cv.cv_forces(ta, tc, x, [i for b in dv for i in b], p) for dv in divisions(n, p)])
+    fs = np.array([cv.cv_forces(ta, tc, x, [i for b in dv for i in b], p, use_bf16=use_bf16)
+                   for dv in divisions(n, p)])
     fd = _direct_gauss(x)
     np.testing.assert_allclose(fs.mean(axis=0), fd, rtol=0, atol=1e-13)
+    if use_bf16:
+        c = cv.c_features(tc, x, use_bf16=True)
+        assert np.array_equal(cv.bf16(c), c)  # the rounded c are BF16 numbers
+        assert not np.array_equal(c, cv.features(tc, x, use_bf16=True))
     if n % p == 0:
-        a = cv.features(ta, x)
-        c = cv.features(tc, x)
+        a = cv.features(ta, x, use_bf16)
+        c = cv.c_features(tc, x, use_bf16)
         var = np.mean(np.sum((fs - fd[None]) ** 2, axis=2), axis=0)
         for i in range(n):
             js = [j for j in range(n) if j != i]
