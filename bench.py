@@ -254,7 +254,17 @@ def force_mse(args) -> dict:
 def ensemble_rate(args) -> dict:
     """The batched ensemble: 4096 independent 2-D Gaussian systems, N_s
     log-uniform on [64, 65536], p = 4, 500 steps in one persistent launch
-    recorded into a hipGraph, with the tile from the autotuner."""
+    with the tile from the autotuner.
+
+    The value is the direct launch timed with HIP events on its stream.  The
+    same call in graph form (recorded, instantiated, replayed once) is timed
+    beside it and reported as a cost, not a gain: the graph holds one node.
+    Roofline: a streamed system (N_s > lds_max) moves each particle's 12-byte
+    record and 4-byte PERM word in and out of HBM once per step (32 B per
+    particle-step, plus 8 B of positions in and out per call); an LDS-resident
+    system touches HBM only to load and store its positions once per call
+    (16 B per particle and call).  Each class is also run alone, as an
+    ensemble of its own systems, for its own rate."""
     import numpy as np
     import torch
     import paper_1812_10575_amd as rbm
@@ -262,26 +272,68 @@ def ensemble_rate(args) -> dict:
     import rbm_inputs
     E = rbm_inputs.ENSEMBLE
     n, keys, x0 = rbm_inputs.ensemble()
-    ens = rbm.Ensemble(d=E["d"], kernel=E["kernel"], p=E["p"], sizes=n, seeds=keys, kparam=E["kparam"],
-                       beta=E["beta"], sigma=E["sigma"], dt=E["dt"])
+    steps = E["steps"]
+
+    def make(sizes, seeds):
+        return rbm.Ensemble(d=E["d"], kernel=E["kernel"], p=E["p"], sizes=sizes, seeds=seeds, kparam=E["kparam"],
+                            beta=E["beta"], sigma=E["sigma"], dt=E["dt"])
+
+    ens = make(n, keys)
     x = torch.from_numpy(x0).cuda()
     t0 = time.perf_counter()
     tile = autotune.tune(ens, x, retune=args.retune)
     t_tune = time.perf_counter() - t0
-    ws = torch.empty(rbm.ensemble_workspace_size(ens), dtype=torch.uint8, device=x.device)
-    xr = x.clone()
-    rbm.ensemble_run(ens, xr, 0, 5, ws=ws, graph=True, **tile)  # warm-up
-    xr.copy_(x)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rbm.ensemble_run(ens, xr, 0, E["steps"], ws=ws, graph=True, **tile)
-    dt = time.perf_counter() - t0
-    assert bool(torch.isfinite(xr).all())
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(e, xs, graph):
+        ws = torch.empty(rbm.ensemble_workspace_size(e), dtype=torch.uint8, device=xs.device)
+        xr = xs.clone()
+        rbm.ensemble_run(e, xr, 0, 5, ws=ws, graph=graph, **tile)  # warm-up
+        xr.copy_(xs)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev0.record(stream)
+        rbm.ensemble_run(e, xr, 0, steps, ws=ws, graph=graph, **tile)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        assert bool(torch.isfinite(xr).all())
+        return ev0.elapsed_time(ev1) * 1e-3, wall
+
+    sec, wall = timed(ens, x, False)
+    sec_g, wall_g = timed(ens, x, True)
     tot = int(n.sum())
-    return {"workload": E["name"], "systems": int(len(n)), "particles": tot, "steps": E["steps"], "p": E["p"],
-            "seconds": round(dt, 4), "value": tot * E["steps"] / dt, "unit": "particle-steps/s",
+    lds_max = int(tile.get("lds_max") or 0) or 4 * int(tile.get("wg") or 1024)
+    streamed = n > lds_max
+    n_str, n_res = int(n[streamed].sum()), int(n[~streamed].sum())
+    bytes_str = n_str * (16 + 32 * steps)
+    bytes_res = n_res * 16
+    ach = (bytes_str + bytes_res) / sec / 1e9
+    off = np.concatenate([[0], np.cumsum(n)])
+    classes = {}
+    for name, mask, bps in (("streamed", streamed, 32.0), ("lds_resident", ~streamed, 16.0 / steps)):
+        idx = np.nonzero(mask)[0]
+        rows = np.concatenate([np.arange(off[i], off[i + 1]) for i in idx])
+        xs = torch.from_numpy(np.ascontiguousarray(x0[rows])).cuda()
+        s_c, _ = timed(make(n[idx], keys[idx]), xs, False)
+        pc = int(n[idx].sum())
+        c = {"systems": int(len(idx)), "particles": pc, "seconds_alone": round(s_c, 4),
+             "particle_steps_per_s_alone": pc * steps / s_c, "hbm_bytes_per_particle_step": round(bps, 4)}
+        if name == "streamed":
+            a_c = pc * (16 + 32 * steps) / s_c / 1e9
+            c.update({"achieved_GBps_alone": round(a_c, 1), "frac_alone": round(a_c / HBM_PEAK_GBS, 4)})
+        classes[name] = c
+    return {"workload": E["name"], "systems": int(len(n)), "particles": tot, "steps": steps, "p": E["p"],
+            "seconds": round(sec, 4), "value": tot * steps / sec, "unit": "particle-steps/s",
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_str + bytes_res},
+            "classes": classes,
+            "graph": {"seconds": round(sec_g, 4), "wall_seconds": round(wall_g, 4),
+                      "direct_wall_seconds": round(wall, 4)},
             "tile": tile, "tune_seconds": round(t_tune, 2),
-            "launch": "one persistent kernel replayed from a hipGraph; wall clock around the call"}
+            "launch": "one persistent kernel, direct launch, HIP events on its stream"}
 
 
 def dyson_split(args) -> dict:
@@ -437,7 +489,8 @@ def main() -> int:
     ap.add_argument("--retune", action="store_true", help="ignore the ensemble autotune cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a reference for HBM byte counters)")
-    ap.add_argument("--only", choices=("dyson_split", "wealth", "hamilton", "rbmr", "ensemble"), default=None,
+    ap.add_argument("--only", choices=("dyson_split", "wealth", "hamilton", "rbmr", "ensemble", "force_mse"),
+                    default=None,
                     help="run one extra workload alone and print its JSON object (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -455,10 +508,19 @@ def main() -> int:
         from paper_1812_10575_amd import build as hip_build
         hip_build.build()
 
+    if args.calib_copy:
+        torch.cuda.set_device(torch.device("cuda:0"))
+        a = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     if args.only is not None:
         torch.cuda.set_device(torch.device("cuda:0"))
         fn = {"dyson_split": dyson_split, "wealth": wealth, "hamilton": hamilton, "rbmr": rbmr,
-              "ensemble": ensemble_rate}[args.only]
+              "ensemble": ensemble_rate, "force_mse": force_mse}[args.only]
         print(json.dumps({args.only: fn(args)}), flush=True)
         return 0
 
@@ -468,13 +530,6 @@ def main() -> int:
     x0 = rbm_inputs.workload(w["init"], w["n"], w["seed"])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.calib_copy:
-        a = torch.ones(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     ctx = rbm.rbm_init(prm, torch.from_numpy(x0).to(dev))
     stream = torch.cuda.current_stream()
 
