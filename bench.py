@@ -584,6 +584,12 @@ def main() -> int:
     else:
         roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "kernel": dom}
+    # every data pass against the same peak (the split and the fused sort
+    # are the two memory passes of a fused step)
+    roof["passes"] = {k: {"achieved": round(pb[k] / (phase_ms[k] * 1e-3) / 1e9, 1),
+                          "frac": round(pb[k] / (phase_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "traffic": measured_traffic(k)}
+                      for k in ("split", "sort") if k in pb and phase_ms.get(k, 0.0) > 0.0}
     roof["phase_ms"] = {k: round(v, 5) for k, v in phase_ms.items()}
     roof["events_ms_per_step"] = round(ms_total_ev / args.steps, 5)
     rec = 4 * (w["d"] + 1)

@@ -1235,9 +1235,9 @@ namespace {
 constexpr int SINGLE_TPB = 512;
 constexpr int SINGLE_CAP = RBM_SINGLE_CAP;
 constexpr int SINGLE_SBITS = 11;
-constexpr int SORT_TPB = 512;
+constexpr int SORT_TPB = RBM_SORT_TPB;
 constexpr int SORT_CAP = RBM_SORT_CAP;
-constexpr int SORT_SBITS = 11;
+constexpr int SORT_SBITS = RBM_SORT_SBITS;
 static_assert((RBM_MAX_FINE >> 7) <= LVL_NB && (1 << RBM_SPLIT_SHIFT) <= LVL_NB && RBM_SPLIT_SHIFT <= 7,
               "digits beyond the staging arrays");
 constexpr int DIRECT_TPB = 256;

@@ -18,11 +18,22 @@
 // of LDS, four records per thread, so four workgroups share a CU and the
 // fused sort kernel fits 64 VGPRs (eight waves per SIMD).  Buckets this large
 // keep the coarse buckets few (78 at N = 2^24), so the runs that a scatter
-// writes per coarse bucket are long.
+// writes per coarse bucket are long.  The sizes below are compile-time
+// choices (-D overrides give the same results with other bucket shapes:
+// RBM_SORT_CAP / RBM_SORT_TPB records per thread must stay whole, and
+// 2^RBM_SORT_SBITS sub-buckets a multiple of RBM_SORT_TPB).
 #ifndef RBM_BUCKET_MEAN
 #define RBM_BUCKET_MEAN 1700
 #endif
+#ifndef RBM_SORT_CAP
 #define RBM_SORT_CAP 2048
+#endif
+#ifndef RBM_SORT_TPB
+#define RBM_SORT_TPB 512
+#endif
+#ifndef RBM_SORT_SBITS
+#define RBM_SORT_SBITS 11
+#endif
 #define RBM_KEY_SETS 16
 #define RBM_MAX_FINE 32768
 // Scatter and split workgroups: threads holding a fixed number of records
