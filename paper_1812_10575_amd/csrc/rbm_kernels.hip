@@ -650,8 +650,10 @@ __device__ __forceinline__ Rec<D> member_fixed(const StepArgs &s, const Rec<D> *
         }
     }
     // every member is read before any pair is evaluated (the reads are in
-    // flight together); the own term is left out by a select, so the sum is
-    // the same additions in the same order as skipping it
+    // flight together).  The own term is evaluated too, with its scale
+    // replaced by -0: dx = x - x = +0 exactly, so it adds -0 x +0 = -0 and
+    // leaves every partial sum as it was, so the sum is the same additions
+    // in the same order as skipping it (one select per member, not D)
     constexpr int DK = kdim<D, KERN>();
     float xm[PM][DK];
 #pragma unroll
@@ -669,10 +671,9 @@ __device__ __forceinline__ Rec<D> member_fixed(const StepArgs &s, const Rec<D> *
             dx[c] = xi[c] - xm[j][c];
             r2 = fmaf(dx[c], dx[c], r2);
         }
-        const float sc = pair_scale<KERN>(r2, s.a);
-        const bool other = bs + (uint32_t)j != r;
+        const float sc = bs + (uint32_t)j != r ? pair_scale<KERN>(r2, s.a) : -0.0f;
 #pragma unroll
-        for (int c = 0; c < DK; ++c) f[c] = other ? fmaf(sc, dx[c], f[c]) : f[c];
+        for (int c = 0; c < DK; ++c) f[c] = fmaf(sc, dx[c], f[c]);
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) f[c] *= s.inv_p1;
