@@ -164,3 +164,41 @@ def test_rbmr_dyson_follows_the_analytic_density_at_scale():
         say("t", t_end, "KS", ks, "m2", float(np.mean(y * y)), s / 2)
         assert ks <= 0.01, (t_end, ks)
         assert abs(float(np.mean(y * y)) - s / 2) <= 0.003
+
+
+def test_rbmr_largest_system_and_window():
+    """N = 2^25 (the largest system), p = 2, one default window of 2^22
+    iterations (the largest window): the schedule sort at its limits (8192
+    buckets of 4096 particles, 256 counting workgroups); every particle
+    against the oracle."""
+    n = 1 << 25
+    w = rbm_inputs.params_of("dysonrbmr1d-n2^20-p2", n=n, sigma=1.0 / math.sqrt(n))
+    x0 = rbm_inputs.workload(w["init"], n, w["seed"])
+    niter = 1 << 22
+    say("rbmr N = 2^25, one window of", niter)
+    xg = gpu_run(w, x0, 11, niter)
+    xo = ora.rbmr_run(op(w), 2, 11, niter, x0.astype(np.float64))
+    e = ora.rel_max_error(xg, xo)
+    say("e", e)
+    assert e <= 1e-5
+
+
+def test_rbmr_dense_window_takes_the_long_list_paths():
+    """N = 2^20, p = 8 and a window of 10 N / 8 iterations: each particle is
+    in about 10 batches of the window, so a bucket holds more entries than
+    its workgroup groups in LDS, most particles' lists are longer than the
+    register sort takes (the in-place paths), and the window is about 210
+    levels deep (the default 200 rounds, then the finishing workgroup).
+    Same bits as windows of N/p, and the oracle."""
+    n = 1 << 20
+    w = rbm_inputs.params_of("gauss2d-n1024-p2", n=n, p=8)
+    x0 = rbm_inputs.workload("gauss2d", n, 4)
+    niter = n * 10 // 8
+    say("rbmr dense window", n, niter)
+    dense = gpu_run(w, x0, 3, niter, window=niter)
+    plain = gpu_run(w, x0, 3, niter)
+    assert np.array_equal(dense, plain)
+    xo = ora.rbmr_run(op(w), 8, 3, niter, x0.astype(np.float64))
+    e = ora.rel_max_error(dense, xo)
+    say("e", e)
+    assert e <= 1e-4
