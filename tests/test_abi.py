@@ -125,3 +125,30 @@ def test_fused_steps_size_their_buffers(monkeypatch):
     assert rbm.rbm_workspace_size(P(n=200000)) == small_plain
     # at least 32 key sets of one digit byte per slot and the 4-byte fix-up table
     assert fused - plain >= 32 * n + 4 * n
+
+
+def _al(v):
+    return (v + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("n,p,window,rounds", [
+    (1 << 20, 2, 0, 0), (1 << 20, 8, 1 << 22, 0), (3, 2, 1, 1), (100003, 7, 777, 3), (1 << 25, 2, 0, 0),
+    (4097, 3, 5000, 255)])
+def test_rbmr_workspace_size_is_the_header_formula(n, p, window, rounds):
+    """rbmr_workspace_size against the sum that include/rbm.h states: 16 N +
+    16 window p + two queues of 256 segments of ceil(window / 256) + 512
+    entries + the schedule sort's counts (B buckets of 2^bsh particles, at
+    most 1024 buckets or 4096 particles each; G counting workgroups) + the
+    queue lengths, each part rounded up to 256 bytes (host-only call)."""
+    prm = rbm.Params(d=1, kernel=rbm.RBM_K_SOFTCOULOMB, n=n, p=p, kparam=1.0, beta=1.0, sigma=0.1, dt=1e-3)
+    w = window or min(max(n // p, 1), 1 << 22)
+    r = rounds or min((4 + 2 * p) * -(-(w * p) // n) + (1 if n > (1 << 22) else 0), 255)
+    bsh = 0
+    while -(-n // (1 << bsh)) > 1024 and (1 << bsh) < 4096:
+        bsh += 1
+    B = -(-n // (1 << bsh))
+    G = -(-w // max(4096, -(-w // 256)))
+    segcap = -(-w // 256) + 512
+    want = (_al(16 * n) + _al(8 * w * p) + 2 * _al(4 * w * p) + _al(4 * B * G) + 2 * _al(4 * B)
+            + 2 * _al(4 * 256 * segcap) + _al(4 * 256 * (r + 2)))
+    assert rbm.rbmr_workspace_size(prm, window, rounds) == want
