@@ -18,7 +18,7 @@
 //   k_rbmr_offsets  per bucket, the exclusive scan of those counts over the
 //                   workgroups, and the bucket's total
 //   k_rbmr_scatter  draws again and writes each entry (j, member) into its
-//                   bucket's segment
+//                   bucket's segment (and the bucket starts)
 //   k_rbmr_lists    per bucket, each particle's entries in iteration order:
 //                   succ[j] = the particle's next iteration after entry j's
 //                   (NONE after its last), and the particle's record gets
@@ -31,7 +31,8 @@
 //                   (one atomic add per workgroup and pass, on the length
 //                   of one of NSEG queue segments chosen by the workgroup:
 //                   a single queue counter, taking an add from every
-//                   wavefront, made the rounds twice as slow)
+//                   wavefront, made the first round four times as slow:
+//                   adds to one address are carried out one at a time)
 //   k_rbmr_finish   one workgroup continues the rounds for what is pending
 //                   after the last multi-workgroup round (a window of N/2
 //                   random pairs has depth 11 to 13, and after 8 rounds
