@@ -158,12 +158,24 @@ def cpu_baseline(w: dict, x0) -> dict:
     nt = host_threads()
     v_all, s_all, t_all, used = timed(nt, 8.0)
     v_one, s_one, t_one, _ = timed(1, 8.0)
+    # the direct sum of eq. (1.2) on the same kernel at N = 2^20: 2^12 of the
+    # targets on all threads, the whole step extrapolated from them
+    import rbm_inputs
+    nd, nt_ids = 1 << 20, 1 << 12
+    xd = rbm_inputs.workload(w["init"], nd, w["seed"]).astype(np.float64)
+    ora.set_threads(nt)
+    t0 = time.perf_counter()
+    ora.direct_forces(o, xd, np.arange(nt_ids, dtype=np.uint32))
+    td = time.perf_counter() - t0
     return {"value": v_all, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
             "sample": f"{s_all} full steps of the same workload (N={w['n']}, p={w['p']}) on {used} threads "
                       f"(OpenMP over particles, parallel merge sort of the keys), {t_all:.1f} s; "
                       f"single thread: {s_one} steps, {t_one:.1f} s",
             "single_thread": {"value": v_one, "cores": 1, "steps": s_one, "seconds": round(t_one, 2)},
-            "os_cpu_count": os.cpu_count()}
+            "os_cpu_count": os.cpu_count(),
+            "direct_sum": {"n": nd, "targets": nt_ids, "seconds": round(td, 3), "cores": used,
+                           "pairs_per_s": nt_ids * (nd - 1) / td,
+                           "step_seconds_extrapolated": round(td * nd / nt_ids, 1)}}
 
 
 def force_mse(args) -> dict:
@@ -249,6 +261,38 @@ def force_mse(args) -> dict:
                          "cv_particle_steps_per_s": rate_of(cvctx),
                          "plain_p2_particle_steps_per_s": rate_of(rbm.rbm_init(mk(), x))}}
     return out
+
+
+def mse_sweep(args) -> dict:
+    """Force MSE of plain RBM-1 against the direct sum on the headline
+    system's kernel (3-D attraction-repulsion, a = 0.01) at N = 2^20, for
+    p = 2 .. 32: the mean over 16 divisions and a fixed subset of 2^14
+    particles of |F^RBM - F|^2, beside the Lemma 3.1 prediction
+    (1/(p-1) - 1/(N-1)) Lambda_i from the direct sum's moments at the same
+    positions (the headline's initial law, X0 ~ N(0, I3))."""
+    import numpy as np
+    import torch
+    import paper_1812_10575_amd as rbm
+    from paper_1812_10575_amd import measure
+    import rbm_inputs
+    w = rbm_inputs.params_of("attrep3d-n2^24-p8", n=1 << 20)
+    n = w["n"]
+    x = torch.from_numpy(rbm_inputs.workload(w["init"], n, w["seed"])).cuda()
+    ids = torch.from_numpy(np.random.default_rng(9).choice(n, 1 << 14, replace=False).astype(np.int32)).cuda()
+    prm = rbm.Params(**{k: w[k] for k in FIELDS})
+    fdir, m2 = rbm.direct_moments(prm, x, ids)
+    f64 = fdir.double()
+    lam = ((n - 1) / (n - 2) * (m2.double() - (f64 * f64).sum(dim=1))).cpu().numpy()
+    out = {}
+    for p in (2, 4, 8, 16, 32):
+        ctx = rbm.rbm_init(rbm.Params(**{**{k: w[k] for k in FIELDS}, "n": n, "p": p}), x)
+        acc = 0.0
+        for m in range(16):
+            acc += float(rbm.rbm_force_sqerr(rbm.rbm_forces(ctx, 1000 + m), ids, fdir).cpu()[0])
+        mse = acc / (16 * ids.numel())
+        pred = float(np.mean(measure.lemma_3_1_mse(p, n, lam)))
+        out[str(p)] = {"mse": mse, "lemma_3_1": pred, "ratio": mse / pred}
+    return {"workload": "attrep3d-n2^20", "n": n, "subset": int(ids.numel()), "divisions": 16, "p": out}
 
 
 def ensemble_rate(args) -> dict:
@@ -479,7 +523,7 @@ def main() -> int:
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--p", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mse", action="store_true", help="skip the plain vs control-variate MSE part")
+    ap.add_argument("--no-mse", action="store_true", help="skip the force MSE parts (control variate, p sweep)")
     ap.add_argument("--train-steps", type=int, default=4096)
     ap.add_argument("--train-batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -489,7 +533,8 @@ def main() -> int:
     ap.add_argument("--retune", action="store_true", help="ignore the ensemble autotune cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (a reference for HBM byte counters)")
-    ap.add_argument("--only", choices=("dyson_split", "wealth", "hamilton", "rbmr", "ensemble", "force_mse"),
+    ap.add_argument("--only", choices=("dyson_split", "wealth", "hamilton", "rbmr", "ensemble", "force_mse",
+                                        "mse_sweep"),
                     default=None,
                     help="run one extra workload alone and print its JSON object (for profiling it)")
     args = ap.parse_args()
@@ -520,7 +565,7 @@ def main() -> int:
     if args.only is not None:
         torch.cuda.set_device(torch.device("cuda:0"))
         fn = {"dyson_split": dyson_split, "wealth": wealth, "hamilton": hamilton, "rbmr": rbmr,
-              "ensemble": ensemble_rate, "force_mse": force_mse}[args.only]
+              "ensemble": ensemble_rate, "force_mse": force_mse, "mse_sweep": mse_sweep}[args.only]
         print(json.dumps({args.only: fn(args)}), flush=True)
         return 0
 
@@ -624,6 +669,7 @@ def main() -> int:
         out["direct"] = direct_rate(w, x0)
     if not args.no_mse:
         out["force_mse"] = force_mse(args)
+        out["mse_sweep"] = mse_sweep(args)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_rate(args)
     if not args.no_sweep:
